@@ -1,0 +1,150 @@
+/*
+ * mbh.h -- C ABI of libmbh, the MI355X (gfx950) batched LISA massive-black-
+ * hole-binary log-likelihood of Katz, Marsat, Chua, Babak & Larson (2020),
+ * arXiv:2005.01827.
+ *
+ * The library evaluates, for a batch of walkers, -ln L = 1/2 <d-h|d-h>
+ * summed over the TDI channels A, E, T (Sec. II, Eqs. NLL, innerprod,
+ * innerprodsum), where the template h is built as in Sec. II.A: harmonic-mode
+ * amplitude and phase on a sparse frequency grid (Eq. amp_and_phase), the
+ * time-frequency map t_lm(f) (Eq. t_f) with the t < 0 cut, the Fourier-domain
+ * LISA response (Eq. response and the A, E, T combinations), cubic-spline
+ * interpolation onto the dense grid f_k = k df, and a noise-weighted inner
+ * product with the data.  The data and PSD are uploaded once per context
+ * (Sec. II.A: done once before sampling).
+ *
+ * Conventions shared by all entry points
+ *   - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *     tensors); *_host pointers are host memory.  The caller owns every
+ *     buffer it passes; the context owns its device copies and workspaces.
+ *   - 'stream' is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous on that stream unless stated otherwise.  A
+ *     context must not be used from two host threads or two streams at the
+ *     same time.
+ *   - Calls never abort.  They return an mbh_status; mbh_last_error() gives
+ *     the message of the last failure on that context.
+ *   - A walker whose parameters are physically invalid (q outside (0,1],
+ *     |a_i| > 0.99, M_T <= 0, D_L <= 0, any NaN/inf) or whose template has
+ *     no active mode gets ln L = -inf (resp. the data-only value) with
+ *     status MBH_OK, so that a sampler simply rejects it.
+ *
+ * Parameters: params[B][11] float64, in the paper's order (Sec. II):
+ *   M_T [Msun, detector frame], q = m2/m1 in (0,1], a1, a2 (aligned spins,
+ *   a1 of the heavier body), D_L [Gpc], phi_ref, iota, lambda, beta, psi
+ *   (SSB frame, radians), t_ref [s]; t_coal = t0 + t_ref.
+ */
+#ifndef MBH_H
+#define MBH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mbh_ctx mbh_ctx;
+
+typedef enum {
+    MBH_OK = 0,
+    MBH_EINVAL = -1,  /* bad argument: null pointer, size, mode list, layout */
+    MBH_ENOMEM = -2,  /* device or host allocation failed                  */
+    MBH_EHIP = -3,    /* a HIP runtime call failed                          */
+    MBH_EBATCH = -4   /* B > max_batch of the context                       */
+} mbh_status;
+
+typedef enum {
+    MBH_FP64 = 0,     /* whole path in double precision                     */
+    MBH_FP32C = 1     /* dense stage in float with compensated accumulation */
+} mbh_precision;
+
+typedef struct {
+    double df;             /* 1/T_obs [Hz]; dense bins f_k = k df                  */
+    int64_t k0;            /* first dense bin (k0 >= 1)                            */
+    int64_t n;             /* number of dense bins; k0 + n <= 2^31                 */
+    const double *data;    /* host, [3][n][2]: A, E, T complex128 interleaved      */
+    const double *psd;     /* host, [3][n]: one-sided S_n of A, E, T (all > 0)     */
+    int n_modes;           /* 1..6                                                 */
+    int modes[6][2];       /* (l,m) subset of (2,2),(3,3),(4,4),(2,1),(3,2),(4,3)  */
+    int n_sparse;          /* sparse knots per mode, 8..1024 (256 in the configs)  */
+    double t0;             /* [s]; t_coal = t0 + t_ref                             */
+    int precision;         /* mbh_precision                                        */
+    int max_batch;         /* largest B any call on this context will use          */
+} mbh_ctx_desc;
+
+/* Create a context: validates the descriptor, allocates device memory for
+ * the data, the weights 4 df / S_n, the per-channel prefix sums of
+ * 4 df |d|^2 / S_n and all per-walker workspaces for max_batch walkers, and
+ * uploads the data (Sec. II.A: data and PSD are transferred once).
+ * Synchronous.  On failure *out is NULL and nothing is leaked. */
+mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out);
+
+/* Free every resource of the context (NULL is allowed). Synchronous. */
+void mbh_ctx_destroy(mbh_ctx *ctx);
+
+/* Message of the last failure on ctx (static text if ctx is NULL). */
+const char *mbh_last_error(const mbh_ctx *ctx);
+
+/* Sec. II (11-parameter list, Eq. amp_and_phase, Eq. t_f): per walker, the
+ * physical constants; per mode, the frequency support [f_start, f_end] from
+ * the root of t_lm(f) = 0 and the ringdown cut; the sparse log-spaced knots
+ * and A_lm, phi_lm, t_lm at them.  params_dev: device [B][11]. Results stay
+ * in the context workspace. */
+mbh_status mbh_waveform_gen(mbh_ctx *ctx, const double *params_dev, int B, void *stream);
+
+/* Sec. II (Eq. response, A/E/T from X/Y/Z) and Sec. II.A (spline setup):
+ * T^{A,E,T}_lm(f_j, t_lm(f_j)) at every knot, the orbital delay phase folded
+ * into the phase, then not-a-knot cubic-spline coefficients of the eight
+ * real functions per mode.  Requires a preceding mbh_waveform_gen with the
+ * same B on the same stream. */
+mbh_status mbh_response(mbh_ctx *ctx, int B, void *stream);
+
+/* Sec. II.A (dense interpolation) and Eqs. NLL, innerprod, innerprodsum:
+ * interpolate every mode onto the dense bins of its band, sum modes per
+ * channel, and reduce, per walker, out7_dev[B][7] = {ln L, <d|h>_A, <d|h>_E,
+ * <d|h>_T, <h|h>_A, <h|h>_E, <h|h>_T} (device).  The reduction is
+ * deterministic (fixed order, no floating-point atomics).  Requires a
+ * preceding mbh_response with the same B on the same stream. */
+mbh_status mbh_interp_and_inner(mbh_ctx *ctx, int B, double *out7_dev, void *stream);
+
+/* The three stages above in one call, launched as one captured HIP graph per
+ * (B, stream) after the first call: logL_dev[B] (device) receives ln L. */
+mbh_status mbh_loglike_batch(mbh_ctx *ctx, const double *params_dev, int B, double *logL_dev, void *stream);
+
+/* Dense template of one walker on the context's grid, h_dev[3][n][2]
+ * (device, complex128 interleaved), built by the same kernels as the
+ * likelihood.  Used to synthesise injections on the device. */
+mbh_status mbh_template(mbh_ctx *ctx, const double *params_dev, double *h_dev, void *stream);
+
+/* Copy the sparse stage of walker w (after mbh_response) to host buffers;
+ * any pointer may be NULL.  band_host[nm][4] = {active, klo, khi, 0};
+ * fband_host[nm][2] = {f_start, f_end}; f_host[nm][ns] knots;
+ * fn_host[nm][8][ns] = A, phi, Re/Im T^A, Re/Im T^E, Re/Im T^T;
+ * coef_host[nm][8][ns-1][4].  Synchronous on 'stream'. */
+mbh_status mbh_get_sparse(mbh_ctx *ctx, int w, int64_t *band_host, double *fband_host, double *f_host,
+                          double *fn_host, double *coef_host, void *stream);
+
+/* Replace the sparse stage of walkers 0..B-1 with caller-supplied knots and
+ * knot values (host, same layouts as mbh_get_sparse) and recompute the spline
+ * coefficients on the device; a following mbh_interp_and_inner evaluates
+ * exactly those functions.  Lets the dense stage be checked in isolation.
+ * Synchronous on 'stream'. */
+mbh_status mbh_set_sparse(mbh_ctx *ctx, int B, const int64_t *band_host, const double *fband_host,
+                          const double *f_host, const double *fn_host, void *stream);
+
+/* Kernel timing for measurement.  With on != 0, mbh_loglike_batch launches
+ * its kernels directly (the same kernels and launch shapes as the captured
+ * graph) and brackets the dense interpolation + inner-product kernel with HIP
+ * events on the caller's stream.  mbh_get_timing synchronizes on those
+ * events and returns the summed dense-kernel time [ms] and the number of
+ * timed launches since the last mbh_set_timing call; outputs may be NULL. */
+mbh_status mbh_set_timing(mbh_ctx *ctx, int on);
+mbh_status mbh_get_timing(mbh_ctx *ctx, double *dense_ms_total, int64_t *count);
+
+/* Library version (major*100 + minor). */
+int mbh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MBH_H */

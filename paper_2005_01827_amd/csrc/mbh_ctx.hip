@@ -1,0 +1,475 @@
+// Context management and the exported C ABI of libmbh (see include/mbh.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mbh.h"
+#include "mbh_internal.h"
+
+using namespace mbh;
+
+struct mbh_ctx {
+    mbh_ctx_desc desc;
+    Modes md;
+    GridDesc g;
+    int max_batch;
+    int max_items;
+    int precision;
+    // resident data
+    double2 *d = nullptr;
+    double *w = nullptr;
+    double *pre = nullptr;
+    // workspace
+    Work wk;
+    double *params = nullptr;     // [max_batch][11] staging for graph launches
+    double *logL = nullptr;       // [max_batch]
+    std::vector<void *> allocs;
+    std::map<int, hipGraphExec_t> graphs;   // per batch size
+    hipGraph_t graph_tmp = nullptr;
+    std::string err;
+    int last_B = -1;              // B of the last waveform_gen (stage checks)
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+};
+
+namespace {
+
+const char *kNoCtx = "mbh: null context";
+
+mbh_status fail(mbh_ctx *c, mbh_status st, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return st;
+}
+
+mbh_status hip_fail(mbh_ctx *c, hipError_t e, const char *where)
+{
+    return fail(c, MBH_EHIP, "mbh: %s failed: %s", where, hipGetErrorString(e));
+}
+
+template <typename T>
+mbh_status dalloc(mbh_ctx *c, T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    const char *inj = getenv("MBH_FAULT_INJECT");
+    if (inj && strcmp(inj, "alloc") == 0) return fail(c, MBH_ENOMEM, "mbh: injected allocation failure");
+    void *raw = nullptr;
+    hipError_t e = hipMalloc(&raw, count * sizeof(T));
+    if (e != hipSuccess || raw == nullptr) {
+        (void)hipGetLastError();
+        return fail(c, MBH_ENOMEM, "mbh: hipMalloc of %zu bytes failed", count * sizeof(T));
+    }
+    c->allocs.push_back(raw);
+    *p = static_cast<T *>(raw);
+    return MBH_OK;
+}
+
+void drop_events(mbh_ctx *c)
+{
+    for (auto &ev : c->events) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    c->events.clear();
+}
+
+void release(mbh_ctx *c)
+{
+    drop_events(c);
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    for (void *p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+}
+
+bool mode_ok(int l, int m)
+{
+    return (l == 2 && m == 2) || (l == 3 && m == 3) || (l == 4 && m == 4) || (l == 2 && m == 1) ||
+           (l == 3 && m == 2) || (l == 4 && m == 3);
+}
+
+Data data_of(const mbh_ctx *c) { return Data{c->d, c->w, c->pre}; }
+
+mbh_status check_B(mbh_ctx *c, int B)
+{
+    if (B < 0) return fail(c, MBH_EINVAL, "mbh: negative batch %d", B);
+    if (B > c->max_batch) return fail(c, MBH_EBATCH, "mbh: batch %d exceeds max_batch %d", B, c->max_batch);
+    return MBH_OK;
+}
+
+// The three stages, enqueued on st.
+mbh_status enqueue_all(mbh_ctx *c, const double *params, int B, double *out7, double *logL, hipStream_t st,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
+{
+    hipError_t e;
+    if ((e = launch_waveform(params, B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "waveform");
+    if ((e = launch_response(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "response");
+    if ((e = launch_spline(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "spline");
+    if ((e = launch_walker_bands(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "bands");
+    if ((e = launch_dense(B, c->md, c->g, c->wk, data_of(c), c->max_items, st, ev0, ev1)) != hipSuccess)
+        return hip_fail(c, e, "dense");
+    if ((e = launch_reduce(B, c->g, c->wk, data_of(c), out7, logL, st)) != hipSuccess) return hip_fail(c, e, "reduce");
+    return MBH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mbh_version(void) { return 100; }
+
+const char *mbh_last_error(const mbh_ctx *ctx) { return ctx ? ctx->err.c_str() : kNoCtx; }
+
+mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
+{
+    if (!out) return MBH_EINVAL;
+    *out = nullptr;
+    if (!desc || !desc->data || !desc->psd) return MBH_EINVAL;
+    if (!(desc->df > 0.0) || !std::isfinite(desc->df) || desc->k0 < 1 || desc->n < 4 ||
+        desc->k0 + desc->n > (int64_t)0x7fffffff)
+        return MBH_EINVAL;
+    if (desc->n_modes < 1 || desc->n_modes > kMaxModes) return MBH_EINVAL;
+    if (desc->n_sparse < 8 || desc->n_sparse > 1024) return MBH_EINVAL;
+    if (desc->max_batch < 1 || desc->max_batch > (1 << 16)) return MBH_EINVAL;
+    if (desc->precision != MBH_FP64 && desc->precision != MBH_FP32C) return MBH_EINVAL;
+    if (!std::isfinite(desc->t0)) return MBH_EINVAL;
+    for (int i = 0; i < desc->n_modes; ++i) {
+        if (!mode_ok(desc->modes[i][0], desc->modes[i][1])) return MBH_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (desc->modes[i][0] == desc->modes[j][0] && desc->modes[i][1] == desc->modes[j][1]) return MBH_EINVAL;
+    }
+    const int64_t n = desc->n;
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!(desc->psd[i] > 0.0) || !std::isfinite(desc->psd[i])) return MBH_EINVAL;
+
+    mbh_ctx *c = new (std::nothrow) mbh_ctx();
+    if (!c) return MBH_ENOMEM;
+    c->desc = *desc;
+    c->desc.data = nullptr;
+    c->desc.psd = nullptr;
+    c->md.nm = desc->n_modes;
+    for (int i = 0; i < kMaxModes; ++i) {
+        c->md.l[i] = i < desc->n_modes ? desc->modes[i][0] : 0;
+        c->md.m[i] = i < desc->n_modes ? desc->modes[i][1] : 0;
+    }
+    c->g.df = desc->df;
+    c->g.t0 = desc->t0;
+    c->g.k0 = (int)desc->k0;
+    c->g.n = (int)n;
+    c->g.ns = desc->n_sparse;
+    c->max_batch = desc->max_batch;
+    c->precision = desc->precision;
+    const long long ntile_max = (n + kTileBins - 1) / kTileBins + 1;
+    const long long items = (long long)desc->max_batch * ntile_max;
+    if (items > 0x7fffffffLL) { delete c; return MBH_EINVAL; }
+    c->max_items = (int)items;
+
+    const int B = desc->max_batch, nm = desc->n_modes, ns = desc->n_sparse;
+    mbh_status st = MBH_OK;
+    double *psd_dev = nullptr, *scratch = nullptr;
+    const size_t nchunks = (size_t)((n + 2047) / 2048);
+#define TRY(x)                       \
+    do {                             \
+        if ((st = (x)) != MBH_OK) {  \
+            release(c);              \
+            delete c;                \
+            return st;               \
+        }                            \
+    } while (0)
+    TRY(dalloc(c, &c->d, (size_t)3 * n));
+    TRY(dalloc(c, &c->w, (size_t)3 * n));
+    TRY(dalloc(c, &c->pre, (size_t)3 * (n + 1)));
+    TRY(dalloc(c, &psd_dev, (size_t)3 * n));
+    TRY(dalloc(c, &scratch, (size_t)3 * n + 3 * nchunks));
+    TRY(dalloc(c, &c->wk.src, (size_t)B));
+    TRY(dalloc(c, &c->wk.band, (size_t)B * nm));
+    TRY(dalloc(c, &c->wk.wband, (size_t)B));
+    TRY(dalloc(c, &c->wk.kf, (size_t)B * nm * ns));
+    TRY(dalloc(c, &c->wk.kt, (size_t)B * nm * ns));
+    TRY(dalloc(c, &c->wk.fn, (size_t)B * nm * kNumFn * ns));
+    TRY(dalloc(c, &c->wk.coef, (size_t)B * nm * (ns - 1) * kCoefPerIv));
+    TRY(dalloc(c, &c->wk.spline_scratch, (size_t)B * nm * kNumFn * 2 * ns));
+    TRY(dalloc(c, &c->wk.item_w, (size_t)c->max_items));
+    TRY(dalloc(c, &c->wk.wbase, (size_t)B + 1));
+    TRY(dalloc(c, &c->wk.partial, (size_t)c->max_items * kPartials));
+    TRY(dalloc(c, &c->wk.out7, (size_t)B * 7));
+    TRY(dalloc(c, &c->params, (size_t)B * 11));
+    TRY(dalloc(c, &c->logL, (size_t)B));
+#undef TRY
+    hipError_t e;
+    if ((e = hipMemcpy(c->d, desc->data, sizeof(double) * 6 * n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(psd_dev, desc->psd, sizeof(double) * 3 * n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = launch_setup_data(psd_dev, c->d, c->w, c->pre, scratch, c->g, 4.0 * desc->df, nullptr)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess) {
+        release(c);
+        delete c;
+        return MBH_EHIP;
+    }
+    // the PSD copy and setup scratch are no longer needed
+    for (auto it = c->allocs.begin(); it != c->allocs.end();) {
+        if (*it == psd_dev || *it == scratch) {
+            (void)hipFree(*it);
+            it = c->allocs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    *out = c;
+    return MBH_OK;
+}
+
+void mbh_ctx_destroy(mbh_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    release(ctx);
+    delete ctx;
+}
+
+mbh_status mbh_waveform_gen(mbh_ctx *ctx, const double *params_dev, int B, void *stream)
+{
+    if (!ctx) return MBH_EINVAL;
+    mbh_status st = check_B(ctx, B);
+    if (st) return st;
+    if (B > 0 && !params_dev) return fail(ctx, MBH_EINVAL, "mbh: null params");
+    hipError_t e = launch_waveform(params_dev, B, ctx->md, ctx->g, ctx->wk, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "waveform_gen");
+    ctx->last_B = B;
+    return MBH_OK;
+}
+
+mbh_status mbh_response(mbh_ctx *ctx, int B, void *stream)
+{
+    if (!ctx) return MBH_EINVAL;
+    mbh_status st = check_B(ctx, B);
+    if (st) return st;
+    hipError_t e = launch_response(B, ctx->md, ctx->g, ctx->wk, (hipStream_t)stream);
+    if (e == hipSuccess) e = launch_spline(B, ctx->md, ctx->g, ctx->wk, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "response");
+    return MBH_OK;
+}
+
+mbh_status mbh_interp_and_inner(mbh_ctx *ctx, int B, double *out7_dev, void *stream)
+{
+    if (!ctx) return MBH_EINVAL;
+    mbh_status st = check_B(ctx, B);
+    if (st) return st;
+    if (B > 0 && !out7_dev) return fail(ctx, MBH_EINVAL, "mbh: null out7");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_walker_bands(B, ctx->md, ctx->g, ctx->wk, s);
+    if (e == hipSuccess) e = launch_dense(B, ctx->md, ctx->g, ctx->wk, data_of(ctx), ctx->max_items, s);
+    if (e == hipSuccess) e = launch_reduce(B, ctx->g, ctx->wk, data_of(ctx), out7_dev, nullptr, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "interp_and_inner");
+    return MBH_OK;
+}
+
+mbh_status mbh_loglike_batch(mbh_ctx *ctx, const double *params_dev, int B, double *logL_dev, void *stream)
+{
+    if (!ctx) return MBH_EINVAL;
+    mbh_status st = check_B(ctx, B);
+    if (st) return st;
+    if (B == 0) return MBH_OK;
+    if (!params_dev || !logL_dev) return fail(ctx, MBH_EINVAL, "mbh: null params or logL");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(ctx->params, params_dev, sizeof(double) * 11 * B, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "params copy");
+    if (ctx->timing) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(ctx, e, "event create");
+        if ((e = hipEventCreate(&e1)) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return hip_fail(ctx, e, "event create");
+        }
+        ctx->events.emplace_back(e0, e1);
+        st = enqueue_all(ctx, ctx->params, B, ctx->wk.out7, ctx->logL, s, e0, e1);
+        if (st != MBH_OK) return st;
+        e = hipMemcpyAsync(logL_dev, ctx->logL, sizeof(double) * B, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "logL copy");
+        ctx->last_B = B;
+        return MBH_OK;
+    }
+    auto it = ctx->graphs.find(B);
+    if (it == ctx->graphs.end()) {
+        // capture the fixed sequence of kernels for this batch size on a
+        // private stream, then instantiate it
+        hipStream_t cap;
+        if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return hip_fail(ctx, e, "stream");
+        hipGraph_t graph = nullptr;
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            st = enqueue_all(ctx, ctx->params, B, ctx->wk.out7, ctx->logL, cap);
+            hipError_t e2 = hipStreamEndCapture(cap, &graph);
+            if (st == MBH_OK && e2 != hipSuccess) st = hip_fail(ctx, e2, "end capture");
+        } else {
+            st = hip_fail(ctx, e, "begin capture");
+        }
+        (void)hipStreamDestroy(cap);
+        if (st != MBH_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(ctx, e, "graph instantiate");
+        it = ctx->graphs.emplace(B, exec).first;
+    }
+    if ((e = hipGraphLaunch(it->second, s)) != hipSuccess) return hip_fail(ctx, e, "graph launch");
+    e = hipMemcpyAsync(logL_dev, ctx->logL, sizeof(double) * B, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "logL copy");
+    ctx->last_B = B;
+    return MBH_OK;
+}
+
+mbh_status mbh_set_timing(mbh_ctx *ctx, int on)
+{
+    if (!ctx) return MBH_EINVAL;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(ctx, e, "sync");
+    drop_events(ctx);
+    ctx->timing = on != 0;
+    return MBH_OK;
+}
+
+mbh_status mbh_get_timing(mbh_ctx *ctx, double *dense_ms_total, int64_t *count)
+{
+    if (!ctx) return MBH_EINVAL;
+    double total = 0.0;
+    for (auto &ev : ctx->events) {
+        hipError_t e = hipEventSynchronize(ev.second);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.first, ev.second);
+        if (e != hipSuccess) return hip_fail(ctx, e, "event timing");
+        total += ms;
+    }
+    if (dense_ms_total) *dense_ms_total = total;
+    if (count) *count = (int64_t)ctx->events.size();
+    return MBH_OK;
+}
+
+mbh_status mbh_template(mbh_ctx *ctx, const double *params_dev, double *h_dev, void *stream)
+{
+    if (!ctx) return MBH_EINVAL;
+    if (!params_dev || !h_dev) return fail(ctx, MBH_EINVAL, "mbh: null params or h");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemsetAsync(h_dev, 0, sizeof(double) * 6 * (size_t)ctx->g.n, s);
+    if (e == hipSuccess) e = launch_waveform(params_dev, 1, ctx->md, ctx->g, ctx->wk, s);
+    if (e == hipSuccess) e = launch_response(1, ctx->md, ctx->g, ctx->wk, s);
+    if (e == hipSuccess) e = launch_spline(1, ctx->md, ctx->g, ctx->wk, s);
+    if (e == hipSuccess) e = launch_walker_bands(1, ctx->md, ctx->g, ctx->wk, s);
+    if (e == hipSuccess) e = launch_template(ctx->md, ctx->g, ctx->wk, reinterpret_cast<double2 *>(h_dev), s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "template");
+    ctx->last_B = 1;
+    return MBH_OK;
+}
+
+mbh_status mbh_get_sparse(mbh_ctx *ctx, int w, int64_t *band_host, double *fband_host, double *f_host,
+                          double *fn_host, double *coef_host, void *stream)
+{
+    if (!ctx) return MBH_EINVAL;
+    if (w < 0 || w >= ctx->max_batch) return fail(ctx, MBH_EINVAL, "mbh: walker index %d out of range", w);
+    const int nm = ctx->md.nm, ns = ctx->g.ns;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sync");
+    if (band_host || fband_host) {
+        std::vector<ModeBand> b(nm);
+        if ((e = hipMemcpy(b.data(), ctx->wk.band + (size_t)w * nm, sizeof(ModeBand) * nm, hipMemcpyDeviceToHost)) != hipSuccess)
+            return hip_fail(ctx, e, "copy band");
+        for (int i = 0; i < nm; ++i) {
+            if (band_host) {
+                band_host[4 * i] = b[i].active;
+                band_host[4 * i + 1] = b[i].klo;
+                band_host[4 * i + 2] = b[i].khi;
+                band_host[4 * i + 3] = 0;
+            }
+            if (fband_host) {
+                fband_host[2 * i] = b[i].fs;
+                fband_host[2 * i + 1] = b[i].fe;
+            }
+        }
+    }
+    if (f_host && (e = hipMemcpy(f_host, ctx->wk.kf + (size_t)w * nm * ns, sizeof(double) * nm * ns, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(ctx, e, "copy knots");
+    if (fn_host && (e = hipMemcpy(fn_host, ctx->wk.fn + (size_t)w * nm * kNumFn * ns, sizeof(double) * nm * kNumFn * ns,
+                                  hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(ctx, e, "copy values");
+    if (coef_host) {
+        // device layout [nm][ns-1][8][4] -> host layout [nm][8][ns-1][4]
+        std::vector<double> tmp((size_t)nm * (ns - 1) * kCoefPerIv);
+        if ((e = hipMemcpy(tmp.data(), ctx->wk.coef + (size_t)w * nm * (ns - 1) * kCoefPerIv, sizeof(double) * tmp.size(),
+                           hipMemcpyDeviceToHost)) != hipSuccess)
+            return hip_fail(ctx, e, "copy coefficients");
+        for (int im = 0; im < nm; ++im)
+            for (int i = 0; i < ns - 1; ++i)
+                for (int q = 0; q < kNumFn; ++q)
+                    for (int c = 0; c < 4; ++c)
+                        coef_host[(((size_t)im * kNumFn + q) * (ns - 1) + i) * 4 + c] =
+                            tmp[(((size_t)im * (ns - 1) + i) * kNumFn + q) * 4 + c];
+    }
+    return MBH_OK;
+}
+
+mbh_status mbh_set_sparse(mbh_ctx *ctx, int B, const int64_t *band_host, const double *fband_host,
+                          const double *f_host, const double *fn_host, void *stream)
+{
+    if (!ctx) return MBH_EINVAL;
+    mbh_status st = check_B(ctx, B);
+    if (st) return st;
+    if (B > 0 && (!band_host || !fband_host || !f_host || !fn_host)) return fail(ctx, MBH_EINVAL, "mbh: null input");
+    const int nm = ctx->md.nm, ns = ctx->g.ns;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<ModeBand> b((size_t)B * nm);
+    std::vector<Source> src(B);
+    for (int w = 0; w < B; ++w) {
+        std::memset(&src[w], 0, sizeof(Source));
+        src[w].valid = 1;
+        for (int i = 0; i < nm; ++i) {
+            ModeBand &mb = b[(size_t)w * nm + i];
+            std::memset(&mb, 0, sizeof(ModeBand));
+            const int64_t *bh = band_host + ((size_t)w * nm + i) * 4;
+            if (bh[0] && (bh[1] < ctx->g.k0 || bh[2] >= (int64_t)ctx->g.k0 + ctx->g.n || bh[2] < bh[1] + 3))
+                return fail(ctx, MBH_EINVAL, "mbh: band of walker %d mode %d outside the grid", w, i);
+            const double *fk = f_host + ((size_t)w * nm + i) * ns;
+            if (bh[0]) {
+                for (int j = 0; j + 1 < ns; ++j)
+                    if (!(fk[j + 1] > fk[j])) return fail(ctx, MBH_EINVAL, "mbh: knots not increasing");
+                if (fk[0] > (double)bh[1] * ctx->g.df || fk[ns - 1] < (double)bh[2] * ctx->g.df)
+                    return fail(ctx, MBH_EINVAL, "mbh: knots do not cover the band");
+            }
+            mb.active = (int)bh[0];
+            mb.klo = (int)bh[1];
+            mb.khi = (int)bh[2];
+            mb.fs = fband_host[((size_t)w * nm + i) * 2];
+            mb.fe = fband_host[((size_t)w * nm + i) * 2 + 1];
+        }
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(ctx->wk.src, src.data(), sizeof(Source) * B, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->wk.band, b.data(), sizeof(ModeBand) * b.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->wk.kf, f_host, sizeof(double) * B * nm * ns, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(ctx->wk.fn, fn_host, sizeof(double) * B * nm * kNumFn * ns, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_spline(B, ctx->md, ctx->g, ctx->wk, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set_sparse");
+    ctx->last_B = B;
+    return MBH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Device-side data structures and kernel launchers shared by the HIP
+// translation units of libmbh.  Everything here is GPU-path code; the CPU
+// oracle neither includes nor links it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mbh {
+
+constexpr int kMaxModes = 6;
+constexpr int kNumFn = 8;          // A, phi, Re/Im T^A, Re/Im T^E, Re/Im T^T
+constexpr int kCoefPerIv = kNumFn * 4;  // 32 doubles per sparse interval
+
+// Dense tiling of the frequency axis: a work item is (walker, tile) with
+// kTileBins consecutive bins, processed by kDenseThreads threads that each
+// take kDenseJ bins strided by kDenseThreads (coalesced loads of d and w).
+constexpr int kDenseThreads = 256;
+constexpr int kDenseJ = 4;
+constexpr int kTileBins = kDenseThreads * kDenseJ;
+constexpr int kPartials = 9;       // R_c, DH_c, HH_c for c = A, E, T
+
+// Per-walker constants of the waveform model (built by the source kernel).
+struct Source {
+    double M, eta, delta, x1, x2, chi1, chi2, Dl;
+    double phiref, iota, lam, beta, psi, tcoal;
+    double p2, p3, p4, p5, p6, p6L, p7;     // TaylorF2 coefficients
+    double af, Mfin, fRD, fd;               // remnant spin, mass, (2,2,0) QNM
+    double fJ, kRD, cR, b1, b0;             // merger-ringdown phase piece
+    double fpeak, al0, al1;                 // alignment at max f^2 A_22
+    double A0;                              // amplitude scale
+    int valid;
+    int pad;
+};
+
+// Frequency support of one (walker, mode).
+struct ModeBand {
+    double fs, fe;      // [f_start, f_end]
+    int klo, khi;       // covered dense bins, inclusive
+    int active;         // >= 4 covered bins
+    int pad;
+    double kp[2], kc[2];  // plus/cross weights of the mode (complex)
+};
+
+// Union band of one walker and its work-item range.
+struct WalkerBand {
+    int klo, khi;       // union of the active mode bands, inclusive
+    int tile_lo;        // first tile index (tiles counted from bin k0)
+    int ntiles;         // 0 if the walker has no active mode or is invalid
+};
+
+struct Modes {
+    int nm;
+    int l[kMaxModes];
+    int m[kMaxModes];
+};
+
+struct GridDesc {
+    double df;
+    double t0;
+    int k0;
+    int n;
+    int ns;             // sparse knots per mode
+};
+
+// Device workspace of a context (all pointers device memory).
+struct Work {
+    Source *src;            // [B]
+    ModeBand *band;         // [B][nm]
+    WalkerBand *wband;      // [B]
+    double *kf;             // [B][nm][ns]        knots
+    double *kt;             // [B][nm][ns]        t_lm at the knots
+    double *fn;             // [B][nm][8][ns]     function values at the knots
+    double *coef;           // [B][nm][ns-1][8][4] spline coefficients
+    double *spline_scratch; // [B][nm][8][2 ns]
+    int *item_w;            // [max items] walker of each work item
+    int *wbase;             // [B+1]  exclusive scan of ntiles; wbase[B] = total
+    double *partial;        // [max items][9]
+    double *out7;           // [B][7] default output
+};
+
+// Data resident for the life of a context.
+struct Data {
+    const double2 *d;       // [3][n]   A, E, T data
+    const double *w;        // [3][n]   4 df / S_n
+    const double *pre;      // [3][n+1] prefix sums of |d|^2 w
+};
+
+// ---- launchers (each defined next to its kernels) ----
+hipError_t launch_setup_data(const double *psd, const double2 *d, double *w, double *pre, double *scratch,
+                             const GridDesc &g, double df4, hipStream_t st);
+
+hipError_t launch_waveform(const double *params, int B, const Modes &md, const GridDesc &g, const Work &wk,
+                           hipStream_t st);
+
+hipError_t launch_response(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st);
+
+hipError_t launch_spline(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st);
+
+hipError_t launch_walker_bands(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st);
+
+// ev0/ev1 (optional) are recorded on st right before and after the dense kernel.
+hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &wk, const Data &dt,
+                        int max_items, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+hipError_t launch_reduce(int B, const GridDesc &g, const Work &wk, const Data &dt, double *out7,
+                         double *logL, hipStream_t st);
+
+hipError_t launch_template(const Modes &md, const GridDesc &g, const Work &wk, double2 *h, hipStream_t st);
+
+}  // namespace mbh

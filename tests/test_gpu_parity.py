@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
+the same seeded inputs.
+
+Tolerance (FP64 path): |lnL_gpu - lnL_oracle| <= 1e-10 max(|lnL|, 1); the
+inner products <d|h>_c, <h|h>_c to 1e-10 of sqrt(<h|h>) <d|d>-scale.  Integer
+results (band edges, active flags) must match exactly."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2005_01827_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+
+
+def _lnl_close(g, o):
+    g, o = np.asarray(g), np.asarray(o)
+    both_inf = np.isneginf(g) & np.isneginf(o)
+    ok = both_inf | (np.abs(g - o) <= RTOL * np.maximum(np.abs(o), 1.0))
+    return ok
+
+
+def _report(name, g, o):
+    err = np.abs(np.asarray(g) - np.asarray(o)) / np.maximum(np.abs(np.asarray(o)), 1.0)
+    err = err[np.isfinite(err)]
+    print(f"[{name}] max rel err {err.max() if err.size else 0:.3e}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def small(oracle):
+    import torch
+    from paper_2005_01827_amd import mbh
+    w = inputs.small_config(8, seed=7)
+    g = w.grid
+    psd = inputs.psd_aet(g.freqs)
+    h = oracle.template(w.injection, g, w.modes, w.ns, w.t0)
+    d = h + inputs.noise(g, psd, 77)
+    L = mbh.Likelihood(g, d, psd, w.modes, w.ns, w.t0, max_batch=64)
+    yield w, psd, d, L
+    L.close()
+    torch.cuda.synchronize()
+
+
+def test_sparse_stage_matches_oracle(small, oracle):
+    w, psd, d, L = small
+    print("case: sparse stage, small grid, 8 walkers", flush=True)
+    B = L.waveform_gen(w.walkers)
+    L.response(B)
+    for i in range(B):
+        g = L.get_sparse(i)
+        o = oracle.sparse(w.walkers[i], w.grid, w.modes, w.ns, w.t0)
+        assert np.array_equal(g["band"], o["band"]), (i, g["band"], o["band"])
+        assert np.allclose(g["fband"], o["fband"], rtol=1e-14, atol=0)
+        assert np.allclose(g["f"], o["f"], rtol=1e-14, atol=0)
+        for q in range(8):
+            scale = np.abs(o["fn"][:, q]).max(axis=1, keepdims=True) + 1e-300
+            err = np.abs(g["fn"][:, q] - o["fn"][:, q]) / scale
+            assert err.max() < 1e-11, (i, q, err.max())
+        # spline coefficients: compare each term's size over its interval
+        hpow = np.diff(o["f"], axis=1)[:, None, :, None] ** np.arange(4)
+        scale = np.abs(o["fn"]).max(axis=2)[:, :, None, None] + 1e-300
+        err = np.abs(g["cf"] - o["cf"]) * hpow / scale
+        assert err.max() < 1e-10, (i, err.max())
+
+
+def test_dense_stage_on_oracle_sparse_functions(small, oracle):
+    """Dense interpolation + inner products fed the oracle's own knots and
+    knot values: isolates the dense kernel and the device spline setup."""
+    import torch
+    w, psd, d, L = small
+    print("case: dense stage on oracle sparse arrays, 8 walkers", flush=True)
+    sps = [oracle.sparse(th, w.grid, w.modes, w.ns, w.t0) for th in w.walkers]
+    B = L.set_sparse(np.stack([s["band"] for s in sps]), np.stack([s["fband"] for s in sps]),
+                     np.stack([s["f"] for s in sps]), np.stack([s["fn"] for s in sps]))
+    out = L.interp_and_inner(B)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = oracle.loglike(w.walkers, w.grid, d, psd, w.modes, w.ns, w.t0)
+    _report("dense-on-oracle-sparse", got[:, 0], ref[:, 0])
+    assert np.all(_lnl_close(got[:, 0], ref[:, 0]))
+    hh = ref[:, 4:7].sum(1, keepdims=True)
+    assert np.allclose(got[:, 1:], ref[:, 1:], rtol=0, atol=1e-10 * 10 * (hh + 1))
+
+
+def test_loglike_small_grid_all_stages(small, oracle):
+    import torch
+    w, psd, d, L = small
+    print("case: three stages, small grid, 8 walkers", flush=True)
+    out = L.stages(w.walkers)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ref = oracle.loglike(w.walkers, w.grid, d, psd, w.modes, w.ns, w.t0)
+    _report("stages-small", got[:, 0], ref[:, 0])
+    assert np.all(_lnl_close(got[:, 0], ref[:, 0]))
+    hh = ref[:, 4:7].sum(1, keepdims=True)
+    assert np.allclose(got[:, 1:], ref[:, 1:], rtol=0, atol=1e-9 * (hh + 1))
+    # the graph-launched entry point gives the same bits
+    lnl = L.loglike(w.walkers)
+    torch.cuda.synchronize()
+    assert np.array_equal(lnl.cpu().numpy(), got[:, 0])
+
+
+def test_determinism_and_batch_composition(small):
+    import torch
+    w, psd, d, L = small
+    print("case: determinism / batch composition", flush=True)
+    a = L.loglike(w.walkers).cpu().numpy()
+    b = L.loglike(w.walkers).cpu().numpy()
+    assert np.array_equal(a, b)
+    perm = np.random.default_rng(1).permutation(len(w.walkers))
+    big = np.concatenate([w.walkers[perm], w.walkers[:3]])
+    c = L.loglike(big).cpu().numpy()
+    assert np.array_equal(c[:len(perm)], a[perm])
+    assert np.array_equal(c[len(perm):], a[:3])
+    one = L.loglike(w.walkers[5:6]).cpu().numpy()
+    assert np.array_equal(one, a[5:6])
+    torch.cuda.synchronize()
+
+
+def test_noiseless_injection_from_gpu_template_is_zero(small):
+    import torch
+    from paper_2005_01827_amd import mbh
+    w, psd, d, L = small
+    print("case: GPU template as data, lnL at injection", flush=True)
+    h = L.template(w.injection).cpu().numpy()
+    L2 = mbh.Likelihood(w.grid, h, psd, w.modes, w.ns, w.t0, max_batch=4)
+    try:
+        out = L2.stages(np.stack([w.injection, w.walkers[0]])).cpu().numpy()
+        torch.cuda.synchronize()
+        assert out[0, 0] == 0.0
+        assert out[1, 0] < 0.0
+    finally:
+        L2.close()
+
+
+def test_template_matches_oracle(small, oracle):
+    w, psd, d, L = small
+    print("case: dense template vs oracle", flush=True)
+    h = L.template(w.walkers[2]).cpu().numpy()
+    o = oracle.template(w.walkers[2], w.grid, w.modes, w.ns, w.t0)
+    scale = np.abs(o).max()
+    assert np.max(np.abs(h - o)) < 1e-9 * scale
+
+
+def test_invalid_and_empty_walkers(small, oracle):
+    import torch
+    w, psd, d, L = small
+    print("case: invalid / empty walkers", flush=True)
+    th = np.repeat(w.injection[None], 5, axis=0)
+    th[1, 1] = 1.5                      # q > 1
+    th[2, 3] = 0.995                    # |a2| > 0.99
+    th[3, 0] = float("nan")
+    th[4, 0] = 1e9                      # ringdown below the band: no active mode
+    out = L.stages(th).cpu().numpy()
+    torch.cuda.synchronize()
+    ref = oracle.loglike(th, w.grid, d, psd, w.modes, w.ns, w.t0)
+    assert np.all(np.isneginf(out[1:4, 0]))
+    assert np.all(_lnl_close(out[[0, 4], 0], ref[[0, 4], 0]))
+    assert np.all(out[4, 1:] == 0.0)
+
+
+def test_status_codes(small):
+    from paper_2005_01827_amd import mbh
+    w, psd, d, L = small
+    with pytest.raises(mbh.MbhError) as e:
+        L.loglike(np.repeat(w.injection[None], 65, axis=0))
+    assert e.value.status == mbh.MBH_EBATCH
+    assert L.lib.mbh_loglike_batch(L.ctx, None, 1, None, None) == mbh.MBH_EINVAL
+    assert L.lib.mbh_loglike_batch(L.ctx, None, 0, None, None) == mbh.MBH_OK
+
+
+def _full_case(oracle, w, n_check, noise_seed, max_batch):
+    import torch
+    from paper_2005_01827_amd import mbh
+    g = w.grid
+    psd = inputs.psd_aet(g.freqs)
+    h = oracle.template(w.injection, g, w.modes, w.ns, w.t0)
+    d = h + inputs.noise(g, psd, noise_seed)
+    L = mbh.Likelihood(g, d, psd, w.modes, w.ns, w.t0, max_batch=max_batch)
+    try:
+        got = L.loglike(w.walkers).cpu().numpy()
+        torch.cuda.synchronize()
+        idx = np.linspace(0, len(w.walkers) - 1, n_check).astype(int)
+        ref = oracle.loglike(w.walkers[idx], g, d, psd, w.modes, w.ns, w.t0, nthreads=min(16, os.cpu_count()))
+        _report(w.name, got[idx], ref[:, 0])
+        assert np.all(_lnl_close(got[idx], ref[:, 0]))
+        assert np.all(np.isfinite(got))
+    finally:
+        L.close()
+
+
+def test_config1_batch1_full_grid(oracle):
+    print("case: T_obs=2^22 grid, injection + 64 perturbations", flush=True)
+    w = inputs.config1(65)
+    w.walkers[0] = w.injection
+    _full_case(oracle, w, 65, 101, 128)
+
+
+@pytest.mark.slow
+def test_config2_1024_walkers_sampled(oracle):
+    print("case: T_obs=2^25 grid, 1024 walkers, 12 checked", flush=True)
+    _full_case(oracle, inputs.config2(1024), 12, 2002, 1024)
+
+
+@pytest.mark.slow
+def test_config3_uneven_sampled(oracle):
+    print("case: T_obs=2^25 grid, 2048 uneven walkers, 16 checked", flush=True)
+    _full_case(oracle, inputs.config3(2048), 16, 2002, 2048)
