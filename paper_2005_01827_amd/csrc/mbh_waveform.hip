@@ -215,7 +215,7 @@ __global__ void k_source(const double *__restrict__ params, int B, double t0, So
     phase22_raw(s, fp, a, b, c);
     s.al0 = a;
     s.al1 = b;
-    s.A0 = 0.8164965809277260327 * sqrt(eta) * 0.8263074871924112 * s.M * s.M / s.Dl;  // sqrt(2/3) pi^{-1/6}
+    s.A0 = sqrt(2.0 * eta / 3.0) * pow(kPi, -1.0 / 6.0) * s.M * s.M / s.Dl;
     out[w] = s;
 }
 
