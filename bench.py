@@ -28,7 +28,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "loglike evals/sec (1024 walkers, 1-yr grid) + %HBM peak; ESS/sec flow vs plain"
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
+FP64_PEAK_TFLOPS = 78.6            # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
+FLOPS_PER_MODE_BIN = 111           # 8 cubics 48, e^{i phi} 37, A e^{i phi} 2, 3 complex MACs 24
+FLOPS_PER_WALKER_BIN = 51          # per channel: d-h 2, |r|^2 w 5, Re(d h*) w 5, |h|^2 w 5
+BYTES_PER_WALKER_BIN = 72          # d (3 x complex128) + w (3 x float64), streamed per walker
+KERNEL_REV = "dense-v7"            # traffic counters are only reused for this kernel revision
 
 
 def parse():
@@ -41,7 +45,21 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense_traffic.json"))
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (5 times) and exit; used to "
+                         "scale the FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    import torch
+    n = mib * 1024 * 1024 // 8
+    src = torch.arange(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": n * 8, "launches": 5}), flush=True)
 
 
 def workload(name, walkers):
@@ -68,6 +86,9 @@ def band_bins(L, B):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the batch is sharded per GPU by design "
                                    "(see the design notes), and --gpus N > 1 is not measured"}))
@@ -113,22 +134,27 @@ def main():
     assert np.array_equal(out.cpu().numpy(), lnl), "timed and graph paths disagree"
 
     bins, mode_bins = band_bins(L, B)
-    bytes_per_bin = 3 * 16 + 3 * 8           # d (complex128, A/E/T) + w (float64, A/E/T)
-    alg_bytes = float(bins.sum()) * bytes_per_bin
-    achieved_gbs = alg_bytes / (dense_avg_ms * 1e-3) / 1e9
+    # algorithmic work of the dense kernel (see the design notes, section 6)
+    alg_flops = float(mode_bins.sum()) * FLOPS_PER_MODE_BIN + float(bins.sum()) * FLOPS_PER_WALKER_BIN
+    achieved_tflops = alg_flops / (dense_avg_ms * 1e-3) / 1e12
+    alg_bytes = float(bins.sum()) * BYTES_PER_WALKER_BIN
+    logical_gbs = alg_bytes / (dense_avg_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(args.traffic_json):
         try:
             tj = json.load(open(args.traffic_json))
-            if tj.get("config") == args.config and tj.get("walkers") == B:
+            if tj.get("config") == args.config and tj.get("walkers") == B and tj.get("kernel_rev") == KERNEL_REV:
                 traffic = tj.get("hbm_bytes_per_launch")
         except Exception:
             traffic = None
-    roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_dense (interp + inner products)", "avg_ms": round(dense_avg_ms, 4),
-                "alg_bytes_per_launch": alg_bytes, "bytes_per_walker_bin": bytes_per_bin,
-                "walker_bins": int(bins.sum()), "mode_bins": int(mode_bins.sum())}
+    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved_tflops / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
+                "kernel": "k_dense (interpolation + mode sum + inner products)", "avg_ms": round(dense_avg_ms, 4),
+                "alg_flops_per_launch": alg_flops, "flops_per_mode_bin": FLOPS_PER_MODE_BIN,
+                "flops_per_walker_bin": FLOPS_PER_WALKER_BIN, "mode_bins": int(mode_bins.sum()),
+                "walker_bins": int(bins.sum()),
+                "hbm_logical": {"bytes_per_walker_bin": BYTES_PER_WALKER_BIN, "bytes_per_launch": alg_bytes,
+                                "GB/s": round(logical_gbs, 1), "frac_of_8TB/s": round(logical_gbs / HBM_PEAK_GBS, 4)}}
 
     result = {
         "metric": METRIC, "value": round(evals_per_s, 1), "unit": "evals/s", "n_gpus": 1,
