@@ -217,3 +217,30 @@ def small_config(n_walkers: int = 8, seed: int = 7) -> Workload:
                     0.62, 2.03, 50.25])
     walkers = ball(inj, n_walkers, 1e-3, seed)
     return Workload(f"small-{n_walkers}walkers-Tobs2^20", grid, 0.9 * T, inj, walkers, noise_seed=seed + 1000)
+
+
+# ---------------------------------------------------------------------------
+# Learned-proposal inputs: coupling-layer permutations, flat parameter arrays
+# and training samples.  Sizes (parameter counts) are passed in; nothing here
+# evaluates the flow.
+# ---------------------------------------------------------------------------
+def flow_perms(dim: int, n_layers: int, seed: int) -> np.ndarray:
+    """[n_layers][dim] int32: one seeded random permutation per layer."""
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.permutation(dim) for _ in range(n_layers)]).astype(np.int32)
+
+
+def flow_params(n_params: int, scale: float, seed: int) -> np.ndarray:
+    """A flat float32 parameter array, iid uniform in [-scale, scale]."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-scale, scale, n_params).astype(np.float32)
+
+
+def banana(n: int, dim: int, seed: int, b: float = 0.6, sx: float = 2.0) -> np.ndarray:
+    """n draws of a curved ('banana') density in dim >= 2 dimensions:
+    x0 ~ N(0, sx^2), x1 = b (x0^2 - sx^2) + N(0, 1), others N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, dim))
+    x[:, 0] *= sx
+    x[:, 1] += b * (x[:, 0] ** 2 - sx * sx)
+    return x
