@@ -50,7 +50,7 @@ def test_inverse_undoes_forward_and_agrees_on_logq():
 
 def test_logdet_equals_finite_difference_jacobian():
     """log q(u) + |z|^2/2 + (dim/2) ln 2pi must equal ln|det dz/du|."""
-    dim, L, H = 6, 4, 16
+    dim, L, H = 11, 4, 16
     perm, p = _flow(dim, L, H, 0.5, 5)
     u0 = np.random.default_rng(6).standard_normal((5, dim))
     z0, lq = F.forward(p, u0, perm, H)
@@ -107,3 +107,22 @@ def test_adam_first_step_closed_form():
     # A second identical gradient keeps mhat = g and vhat = g^2.
     p2, _, _ = F.adam(p1, g, m, v, 2, 0.01)
     assert np.allclose(p2 - p1, p1 - p0, rtol=1e-12, atol=1e-15)
+
+
+def test_layer_split_follows_the_documented_layout():
+    """Layer l keeps perm_l[:ceil(dim/2)] for even l and perm_l[:floor(dim/2)]
+    for odd l unchanged; the other coordinates move."""
+    dim, L, H = 7, 2, 8
+    perm, p = _flow(dim, L, H, 0.5, 13)
+    u = np.random.default_rng(14).standard_normal((16, dim))
+    for keep_layer in range(L):
+        q = p.copy()
+        for l, d in enumerate(F.unflatten(q, dim, L, H)):
+            if l != keep_layer:
+                d["W3"][...] = 0
+                d["b3"][...] = 0
+        z, _ = F.forward(q, u, perm, H)
+        nc = (dim + 1) // 2 if keep_layer % 2 == 0 else dim // 2
+        kept, moved = perm[keep_layer][:nc], perm[keep_layer][nc:]
+        assert np.array_equal(z[:, kept], u[:, kept])
+        assert np.all(np.abs(z[:, moved] - u[:, moved]).max(axis=0) > 1e-3)
