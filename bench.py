@@ -45,6 +45,18 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense_traffic.json"))
+    ap.add_argument("--sampler", type=float, default=0.0, metavar="SECONDS",
+                    help="instead of the throughput line, run the learned-proposal comparison: PT (8 rungs x "
+                         "--sampler-walkers walkers, a = 1.15) on the workload's data, stretch only against "
+                         "stretch + flow, SECONDS of wall time per arm; prints one JSON line")
+    ap.add_argument("--sampler-walkers", type=int, default=512)
+    ap.add_argument("--sampler-rungs", type=int, default=8)
+    ap.add_argument("--schedule-study", action="store_true",
+                    help="instead of the throughput line, time the dense kernel under every launch shape "
+                         "(blocks per CU, one workgroup per walker) and the autotuner's pick; one JSON line")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="instead of the throughput line, compare the FP32C dense stage with FP64 per walker "
+                         "on the workload, at its own SNR and rescaled (via D_L) to SNR 100 and 1000; one JSON line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) and exit; used to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -84,10 +96,152 @@ def band_bins(L, B):
     return bins, mode_bins
 
 
+def sampler_comparison(args):
+    """ESS/s of the T = 1 chain: stretch-move PT against stretch + learned
+    proposal, on the workload's synthetic data, the same start and seeds."""
+    import torch
+    from paper_2005_01827_amd import inputs, mbh
+    from paper_2005_01827_amd import sampler as S
+    nt, nw = args.sampler_rungs, args.sampler_walkers
+    w = workload(args.config, nt * nw)
+    g = w.grid
+    psd = inputs.psd_aet(g.freqs)
+    L0 = mbh.Likelihood(g, np.zeros((3, g.n), complex), psd, w.modes, w.ns, w.t0, max_batch=1)
+    h = L0.template(w.injection).cpu().numpy()
+    L0.close()
+    data = h + inputs.noise(g, psd, w.noise_seed)
+    L = mbh.Likelihood(g, data, psd, w.modes, w.ns, w.t0, max_batch=nt * nw // 2)
+    x0 = inputs.to_sampling(w.walkers).reshape(nt, nw, -1)
+    log = lambda name, rep: print(f"# {name}: {json.dumps(rep)}", file=sys.stderr, flush=True)
+    rep = S.ess_comparison(S.gpu_loglike(L), S.box_logprior(), x0, S.ladder(nt), args.sampler, seeds=(5, 55),
+                           a=1.15, log=log, fit_kwargs={"steps": 600, "lr": 1e-3, "batch": 4096})
+    torch.cuda.synchronize()
+    result = {"metric": "ESS/s at T = 1, stretch + learned proposal vs stretch only", "unit": "ESS/s",
+              "value": rep["stretch_flow"]["ess_per_s"], "baseline_value": rep["stretch"]["ess_per_s"],
+              "gain": rep["ess_per_s_gain"], "higher_is_better": True, "n_gpus": 1, "dtype": "f64",
+              "data": "synthetic (seeded injection + Gaussian noise, analytic PSD)",
+              "config": {"workload": w.name, "rungs": nt, "walkers_per_rung": nw, "stretch_a": 1.15,
+                         "seconds_per_arm": args.sampler, "seeds": [5, 55]},
+              "report": rep}
+    print(json.dumps(result), flush=True)
+    L.close()
+
+
+def schedule_study(args):
+    """Dense-kernel time per sweep under each launch shape.  Load-balance
+    efficiency = (one workgroup per walker time) / (tiled time)."""
+    import torch
+    from paper_2005_01827_amd import inputs, mbh
+    w = workload(args.config, args.walkers)
+    g = w.grid
+    B = len(w.walkers)
+    psd = inputs.psd_aet(g.freqs)
+    L0 = mbh.Likelihood(g, np.zeros((3, g.n), complex), psd, w.modes, w.ns, w.t0, max_batch=1)
+    h = L0.template(w.injection).cpu().numpy()
+    L0.close()
+    data = h + inputs.noise(g, psd, w.noise_seed)
+    L = mbh.Likelihood(g, data, psd, w.modes, w.ns, w.t0, max_batch=B)
+    params = torch.as_tensor(w.walkers, dtype=torch.float64, device="cuda")
+    out = torch.empty(B, dtype=torch.float64, device="cuda")
+    ref = None
+    times = {}
+    shapes = [(b, False) for b in (1, 2, 4, 6, 8, 12, 16)] + [(1, True)]
+    for bpc, one in shapes:
+        L.set_schedule(bpc, one)
+        L.set_timing(True)
+        for _ in range(max(args.steps, 3)):
+            L.loglike(params, out=out)
+        ms, cnt = L.get_timing()
+        L.set_timing(False)
+        lnl = out.cpu().numpy()
+        if ref is None:
+            ref = lnl
+        assert np.array_equal(lnl, ref), "launch shapes disagree"
+        key = "one_workgroup_per_walker" if one else f"tiled_{bpc}_per_cu"
+        times[key] = round(ms / cnt, 4)
+        print(f"# {key}: {times[key]} ms", file=sys.stderr, flush=True)
+    best, best_ms = L.autotune(params, reps=5)
+    tiled_best = min(v for k, v in times.items() if k.startswith("tiled"))
+    bins, mode_bins = band_bins(L, B)
+    result = {"metric": "dense-kernel ms per sweep by launch shape", "unit": "ms", "n_gpus": 1,
+              "config": {"workload": w.name, "walkers": B, "dense_bins": g.n},
+              "band_bins_min_max": [int(bins.min()), int(bins.max())], "mode_bins": int(mode_bins.sum()),
+              "dense_ms": times, "autotune": {"blocks_per_cu": best, "median_ms": round(best_ms, 4)},
+              "load_balance_efficiency_vs_one_workgroup_per_walker":
+                  round(times["one_workgroup_per_walker"] / tiled_best, 3)}
+    print(json.dumps(result), flush=True)
+    L.close()
+
+
+def precision_study(args):
+    """Per-walker |ln L(FP32C) - ln L(FP64)| over the batch, and both against
+    the FP64 CPU oracle on a few walkers, at three signal-to-noise ratios.
+    The template scales as 1/D_L exactly, so SNR is set by rescaling D_L of
+    the injection and of every walker by the same factor."""
+    import torch
+    from paper_2005_01827_amd import inputs, mbh
+    w = workload(args.config, args.walkers)
+    g = w.grid
+    B = len(w.walkers)
+    psd = inputs.psd_aet(g.freqs)
+    L0 = mbh.Likelihood(g, np.zeros((3, g.n), complex), psd, w.modes, w.ns, w.t0, max_batch=1)
+    out7 = L0.stages(w.injection[None])          # <h|h>_c of the injection in columns 4..6
+    hh0 = float(out7[0, 4:7].sum().cpu())
+    snr0 = math.sqrt(hh0)
+    cases = []
+    for snr in (snr0, 100.0, 1000.0):
+        f = snr0 / snr
+        inj = w.injection.copy()
+        inj[4] *= f
+        walkers = w.walkers.copy()
+        walkers[:, 4] *= f
+        h = L0.template(inj).cpu().numpy()
+        data = h + inputs.noise(g, psd, w.noise_seed)
+        res = {}
+        for name, prec in (("fp64", mbh.MBH_FP64), ("fp32c", mbh.MBH_FP32C)):
+            L = mbh.Likelihood(g, data, psd, w.modes, w.ns, w.t0, precision=prec, max_batch=B)
+            res[name] = L.loglike(walkers).cpu().numpy()
+            L.close()
+        d = np.abs(res["fp32c"] - res["fp64"])
+        bound = 1e-6 * snr + 1e-12 * np.abs(res["fp64"]) + 1e-6
+        hist, edges = np.histogram(np.log10(np.maximum(d, 1e-16)), bins=np.arange(-16, 4))
+        case = {"snr": round(snr, 2), "D_L_gpc": round(float(inj[4]), 4),
+                "abs_err_fp32c_vs_fp64": {"max": float(d.max()), "median": float(np.median(d)),
+                                          "p99": float(np.quantile(d, 0.99))},
+                "max_err_over_bound": float((d / bound).max()),
+                "log10_abs_err_histogram": {"edges": [int(e) for e in edges], "counts": [int(c) for c in hist]}}
+        if not args.no_cpu_baseline:
+            from oracle import oracle as O
+            O.build()
+            idx = np.linspace(0, B - 1, min(args.cpu_sample, B)).astype(int)
+            ref = O.loglike(walkers[idx], g, data, psd, w.modes, w.ns, w.t0, nthreads=min(16, os.cpu_count() or 1))
+            case["vs_oracle_sample"] = {
+                "walkers": int(len(idx)),
+                "fp64_max_rel_err": float((np.abs(res["fp64"][idx] - ref[:, 0]) /
+                                           np.maximum(np.abs(ref[:, 0]), 1.0)).max()),
+                "fp32c_max_abs_err": float(np.abs(res["fp32c"][idx] - ref[:, 0]).max())}
+        print(f"# snr {snr:.1f}: {json.dumps(case)}", file=sys.stderr, flush=True)
+        cases.append(case)
+    L0.close()
+    result = {"metric": "FP32C ln L error per walker vs FP64", "unit": "abs ln L", "n_gpus": 1,
+              "config": {"workload": w.name, "walkers": B, "dense_bins": g.n},
+              "bound": "1e-6 SNR + 1e-12 |lnL| + 1e-6", "cases": cases}
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
+    if args.precision_study and args.gpus == 1:
+        precision_study(args)
+        return
+    if args.schedule_study and args.gpus == 1:
+        schedule_study(args)
+        return
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.sampler > 0 and args.gpus == 1:
+        sampler_comparison(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; the batch is sharded per GPU by design "

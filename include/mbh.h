@@ -140,6 +140,81 @@ mbh_status mbh_set_sparse(mbh_ctx *ctx, int B, const int64_t *band_host, const d
 mbh_status mbh_set_timing(mbh_ctx *ctx, int on);
 mbh_status mbh_get_timing(mbh_ctx *ctx, double *dense_ms_total, int64_t *count);
 
+/* Launch shape of the dense interpolation + inner-product kernel (the
+ * batching over sources of Sec. II.A).  blocks_per_cu (1..32) workgroups per
+ * compute unit run a grid-stride loop over (walker, 2048-bin tile) work
+ * items; with one_per_walker != 0 each walker's tiles go to one workgroup
+ * instead (an unbalanced reference schedule for load-balance measurements).
+ * ln L is bitwise identical under every shape.  Drops the context's captured
+ * graphs.  Synchronous.  Default: 8 blocks per CU, tiled. */
+mbh_status mbh_set_schedule(mbh_ctx *ctx, int blocks_per_cu, int one_per_walker);
+mbh_status mbh_get_schedule(const mbh_ctx *ctx, int *blocks_per_cu, int *one_per_walker);
+
+/* Autotuner: run the sparse stages once for params_dev[B][11] (device,
+ * 1 <= B <= max_batch), time the dense kernel with HIP events for every
+ * blocks_per_cu in {2, 4, 6, 8, 12, 16} (median of reps in 1..100 launches),
+ * and keep the fastest as the context's tiled schedule.  best_bpc_host and
+ * best_ms_host (may be NULL) receive the choice and its median time [ms].
+ * Synchronous on 'stream'. */
+mbh_status mbh_autotune(mbh_ctx *ctx, const double *params_dev, int B, int reps, int *best_bpc_host,
+                        double *best_ms_host, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Learned proposal for the sampler: an affine-coupling normalizing flow (a
+ * density q(u) that can be both sampled and evaluated), used as the
+ * independence proposal of a Metropolis-Hastings step next to the stretch
+ * move of Sec. III.A.  FP32, on standardized sampling coordinates u.
+ *
+ * Layer l (0..L-1) reorders the dim coordinates by a permutation
+ * perm[l][0..dim); the first nc[l] reordered coordinates (nc = ceil(dim/2)
+ * for even l, floor(dim/2) for odd l) pass through unchanged and condition
+ * an MLP  nc -> H (tanh) -> H (tanh) -> 2 nt  (nt = dim - nc) whose output o
+ * gives s = tanh(o[0..nt)) and t = o[nt..2nt); the other nt reordered
+ * coordinates map as y = x exp(s) + t.  z = f(u) after L layers and
+ *   log q(u) = -|z|^2/2 - (dim/2) ln(2 pi) + sum_l sum_j s_lj.
+ * Parameters are one flat FP32 array, per layer in this order, each linear
+ * map stored input-major (W[i][j] multiplies input i into output j):
+ *   W1[nc][H], b1[H], W2[H][H], b2[H], W3[H][2 nt], b3[2 nt].
+ * Limits: 2 <= dim <= 32, 1 <= L <= 32, 16 <= H <= 256, 1 <= max_batch <= 2^20.
+ * Device arrays are FP32 and row-major: u, z [n][dim], logq [n].
+ * ------------------------------------------------------------------------ */
+typedef struct mbh_flow mbh_flow;
+
+/* Create a flow for batches of up to max_batch rows.  perm_host[L][dim]
+ * (host; each row a permutation of 0..dim-1) fixes the coordinate order of
+ * every layer; NULL draws the permutations from 'seed'.  Initial weights are
+ * drawn from 'seed' (uniform, scale 1/sqrt(fan-in)) except W3 and b3, which
+ * start at zero so that the initial flow is the identity map.  Synchronous;
+ * on failure *out is NULL and nothing is leaked. */
+mbh_status mbh_flow_create(int dim, int n_layers, int hidden, int max_batch, const int *perm_host, uint64_t seed,
+                           mbh_flow **out);
+void mbh_flow_destroy(mbh_flow *flow);
+/* Message of the last failure on the flow (static text if flow is NULL). */
+const char *mbh_flow_last_error(const mbh_flow *flow);
+/* Length of the flat parameter array (-1 if flow is NULL). */
+int64_t mbh_flow_num_params(const mbh_flow *flow);
+/* perm_host[L][dim] and nc_host[L] (host); either may be NULL. */
+mbh_status mbh_flow_get_layout(const mbh_flow *flow, int *perm_host, int *nc_host);
+/* Copy the flat parameter array to / from host memory.  set_params also
+ * clears the Adam moments and step count.  Synchronous. */
+mbh_status mbh_flow_get_params(mbh_flow *flow, float *params_host);
+mbh_status mbh_flow_set_params(mbh_flow *flow, const float *params_host);
+/* z_dev = f(u_dev) and logq_dev = log q(u_dev) for n <= max_batch rows
+ * (logq_dev may be NULL; z_dev may not alias u_dev). */
+mbh_status mbh_flow_forward(mbh_flow *flow, const float *u_dev, int n, float *z_dev, float *logq_dev, void *stream);
+/* u_dev = f^{-1}(z_dev) and logq_dev = log q(u_dev) (may be NULL): with
+ * z ~ N(0, I) this draws u ~ q. */
+mbh_status mbh_flow_inverse(mbh_flow *flow, const float *z_dev, int n, float *u_dev, float *logq_dev, void *stream);
+/* Training loss  -(1/n) sum_i log q(u_i)  (host, double) and its gradient
+ * with respect to the flat parameters (grad_host, may be NULL).  The
+ * gradient stays on the device for mbh_flow_adam.  Every reduction runs in
+ * a fixed order, so results are bitwise reproducible.  Synchronous. */
+mbh_status mbh_flow_loss_grad(mbh_flow *flow, const float *u_dev, int n, double *loss_host, float *grad_host,
+                              void *stream);
+/* One Adam step (beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias-corrected)
+ * on the gradient of the last mbh_flow_loss_grad; EINVAL if there is none. */
+mbh_status mbh_flow_adam(mbh_flow *flow, float lr, void *stream);
+
 /* Library version (major*100 + minor). */
 int mbh_version(void);
 

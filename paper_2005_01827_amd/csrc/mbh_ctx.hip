@@ -1,6 +1,7 @@
 // Context management and the exported C ABI of libmbh (see include/mbh.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -26,6 +27,8 @@ struct mbh_ctx {
     double2 *d = nullptr;
     double *w = nullptr;
     double *pre = nullptr;
+    float2 *dw32 = nullptr;       // FP32 dense stage only
+    float *sw32 = nullptr;
     // workspace
     Work wk;
     double *params = nullptr;     // [max_batch][11] staging for graph launches
@@ -36,6 +39,7 @@ struct mbh_ctx {
     std::string err;
     int last_B = -1;              // B of the last waveform_gen (stage checks)
     bool timing = false;
+    Schedule sch;                 // dense launch shape (mbh_set_schedule / mbh_autotune)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
 };
 
@@ -88,11 +92,16 @@ void drop_events(mbh_ctx *c)
     c->events.clear();
 }
 
+void drop_graphs(mbh_ctx *c)
+{
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
 void release(mbh_ctx *c)
 {
     drop_events(c);
-    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-    c->graphs.clear();
+    drop_graphs(c);
     for (void *p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
 }
@@ -103,7 +112,7 @@ bool mode_ok(int l, int m)
            (l == 3 && m == 2) || (l == 4 && m == 3);
 }
 
-Data data_of(const mbh_ctx *c) { return Data{c->d, c->w, c->pre}; }
+Data data_of(const mbh_ctx *c) { return Data{c->d, c->w, c->pre, c->dw32, c->sw32}; }
 
 mbh_status check_B(mbh_ctx *c, int B)
 {
@@ -120,8 +129,9 @@ mbh_status enqueue_all(mbh_ctx *c, const double *params, int B, double *out7, do
     if ((e = launch_waveform(params, B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "waveform");
     if ((e = launch_response(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "response");
     if ((e = launch_spline(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "spline");
+    if ((e = launch_coef32(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "coef32");
     if ((e = launch_walker_bands(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "bands");
-    if ((e = launch_dense(B, c->md, c->g, c->wk, data_of(c), c->max_items, st, ev0, ev1)) != hipSuccess)
+    if ((e = launch_dense(B, c->md, c->g, c->wk, data_of(c), c->max_items, c->sch, st, ev0, ev1)) != hipSuccess)
         return hip_fail(c, e, "dense");
     if ((e = launch_reduce(B, c->g, c->wk, data_of(c), out7, logL, st)) != hipSuccess) return hip_fail(c, e, "reduce");
     return MBH_OK;
@@ -172,6 +182,7 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
     c->g.k0 = (int)desc->k0;
     c->g.n = (int)n;
     c->g.ns = desc->n_sparse;
+    c->g.precision = desc->precision;
     c->max_batch = desc->max_batch;
     c->precision = desc->precision;
     const long long ntile_max = (n + kTileBins - 1) / kTileBins + 1;
@@ -204,17 +215,31 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
     TRY(dalloc(c, &c->wk.fn, (size_t)B * nm * kNumFn * ns));
     TRY(dalloc(c, &c->wk.coef, (size_t)B * nm * (ns - 1) * kCoefPerIv));
     TRY(dalloc(c, &c->wk.spline_scratch, (size_t)B * nm * kNumFn * 2 * ns));
+    TRY(dalloc(c, &c->wk.kbin, (size_t)B * nm * ns));
     TRY(dalloc(c, &c->wk.item_w, (size_t)c->max_items));
     TRY(dalloc(c, &c->wk.wbase, (size_t)B + 1));
     TRY(dalloc(c, &c->wk.partial, (size_t)c->max_items * kPartials));
     TRY(dalloc(c, &c->wk.out7, (size_t)B * 7));
+    TRY(dalloc(c, &c->wk.cis_tab, (size_t)32));
+    TRY(dalloc(c, &c->wk.cis32, (size_t)32));
+    if (desc->precision == MBH_FP32C) {
+        TRY(dalloc(c, &c->dw32, (size_t)3 * n));
+        TRY(dalloc(c, &c->sw32, (size_t)3 * n));
+        TRY(dalloc(c, &c->wk.coef32, (size_t)B * nm * (ns - 1) * kCoefPerIv));
+    }
     TRY(dalloc(c, &c->params, (size_t)B * 11));
     TRY(dalloc(c, &c->logL, (size_t)B));
 #undef TRY
     hipError_t e;
-    if ((e = hipMemcpy(c->d, desc->data, sizeof(double) * 6 * n, hipMemcpyHostToDevice)) != hipSuccess ||
+    int ncis = 0, ncis32 = 0;
+    const double *cis_host = cis_table_host(&ncis);
+    const float *cis32_host = cis32_table_host(&ncis32);
+    if ((e = hipMemcpy(c->wk.cis_tab, cis_host, sizeof(double) * ncis, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->wk.cis32, cis32_host, sizeof(float) * ncis32, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d, desc->data, sizeof(double) * 6 * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(psd_dev, desc->psd, sizeof(double) * 3 * n, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = launch_setup_data(psd_dev, c->d, c->w, c->pre, scratch, c->g, 4.0 * desc->df, nullptr)) != hipSuccess ||
+        (e = launch_setup_data(psd_dev, c->d, c->w, c->pre, scratch, c->dw32, c->sw32, c->g, 4.0 * desc->df, nullptr)) !=
+            hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess) {
         release(c);
         delete c;
@@ -260,6 +285,7 @@ mbh_status mbh_response(mbh_ctx *ctx, int B, void *stream)
     if (st) return st;
     hipError_t e = launch_response(B, ctx->md, ctx->g, ctx->wk, (hipStream_t)stream);
     if (e == hipSuccess) e = launch_spline(B, ctx->md, ctx->g, ctx->wk, (hipStream_t)stream);
+    if (e == hipSuccess) e = launch_coef32(B, ctx->md, ctx->g, ctx->wk, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "response");
     return MBH_OK;
 }
@@ -272,7 +298,7 @@ mbh_status mbh_interp_and_inner(mbh_ctx *ctx, int B, double *out7_dev, void *str
     if (B > 0 && !out7_dev) return fail(ctx, MBH_EINVAL, "mbh: null out7");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_walker_bands(B, ctx->md, ctx->g, ctx->wk, s);
-    if (e == hipSuccess) e = launch_dense(B, ctx->md, ctx->g, ctx->wk, data_of(ctx), ctx->max_items, s);
+    if (e == hipSuccess) e = launch_dense(B, ctx->md, ctx->g, ctx->wk, data_of(ctx), ctx->max_items, ctx->sch, s);
     if (e == hipSuccess) e = launch_reduce(B, ctx->g, ctx->wk, data_of(ctx), out7_dev, nullptr, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "interp_and_inner");
     return MBH_OK;
@@ -362,13 +388,89 @@ mbh_status mbh_get_timing(mbh_ctx *ctx, double *dense_ms_total, int64_t *count)
     return MBH_OK;
 }
 
+mbh_status mbh_set_schedule(mbh_ctx *ctx, int blocks_per_cu, int one_per_walker)
+{
+    if (!ctx) return MBH_EINVAL;
+    if (blocks_per_cu < 1 || blocks_per_cu > 32)
+        return fail(ctx, MBH_EINVAL, "mbh: blocks_per_cu %d outside [1, 32]", blocks_per_cu);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(ctx, e, "sync");
+    drop_graphs(ctx);
+    ctx->sch.blocks_per_cu = blocks_per_cu;
+    ctx->sch.one_per_walker = one_per_walker != 0;
+    return MBH_OK;
+}
+
+mbh_status mbh_get_schedule(const mbh_ctx *ctx, int *blocks_per_cu, int *one_per_walker)
+{
+    if (!ctx) return MBH_EINVAL;
+    if (blocks_per_cu) *blocks_per_cu = ctx->sch.blocks_per_cu;
+    if (one_per_walker) *one_per_walker = ctx->sch.one_per_walker;
+    return MBH_OK;
+}
+
+mbh_status mbh_autotune(mbh_ctx *ctx, const double *params_dev, int B, int reps, int *best_bpc_host,
+                        double *best_ms_host, void *stream)
+{
+    if (!ctx) return MBH_EINVAL;
+    if (B < 1) return fail(ctx, MBH_EINVAL, "mbh: autotune needs B >= 1");
+    mbh_status st = check_B(ctx, B);
+    if (st) return st;
+    if (!params_dev) return fail(ctx, MBH_EINVAL, "mbh: null params");
+    if (reps < 1 || reps > 100) return fail(ctx, MBH_EINVAL, "mbh: reps %d outside [1, 100]", reps);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_waveform(params_dev, B, ctx->md, ctx->g, ctx->wk, s);
+    if (e == hipSuccess) e = launch_response(B, ctx->md, ctx->g, ctx->wk, s);
+    if (e == hipSuccess) e = launch_spline(B, ctx->md, ctx->g, ctx->wk, s);
+    if (e == hipSuccess) e = launch_coef32(B, ctx->md, ctx->g, ctx->wk, s);
+    if (e == hipSuccess) e = launch_walker_bands(B, ctx->md, ctx->g, ctx->wk, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "autotune stages");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(ctx, e, "event create");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(ctx, e, "event create");
+    }
+    static const int kCand[] = {2, 4, 6, 8, 12, 16};
+    int best = ctx->sch.blocks_per_cu;
+    double best_ms = 1e300;
+    for (int c : kCand) {
+        Schedule sch;
+        sch.blocks_per_cu = c;
+        std::vector<float> ms;
+        for (int r = 0; r < reps && e == hipSuccess; ++r) {
+            e = launch_dense(B, ctx->md, ctx->g, ctx->wk, data_of(ctx), ctx->max_items, sch, s, e0, e1);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            ms.push_back(t);
+        }
+        if (e != hipSuccess) break;
+        std::sort(ms.begin(), ms.end());
+        const double med = ms[ms.size() / 2];
+        if (med < best_ms) {
+            best_ms = med;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(ctx, e, "autotune");
+    drop_graphs(ctx);
+    ctx->sch.blocks_per_cu = best;
+    ctx->sch.one_per_walker = 0;
+    ctx->last_B = B;
+    if (best_bpc_host) *best_bpc_host = best;
+    if (best_ms_host) *best_ms_host = best_ms;
+    return MBH_OK;
+}
+
 mbh_status mbh_template(mbh_ctx *ctx, const double *params_dev, double *h_dev, void *stream)
 {
     if (!ctx) return MBH_EINVAL;
     if (!params_dev || !h_dev) return fail(ctx, MBH_EINVAL, "mbh: null params or h");
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMemsetAsync(h_dev, 0, sizeof(double) * 6 * (size_t)ctx->g.n, s);
-    if (e == hipSuccess) e = launch_waveform(params_dev, 1, ctx->md, ctx->g, ctx->wk, s);
+    hipError_t e = launch_waveform(params_dev, 1, ctx->md, ctx->g, ctx->wk, s);
     if (e == hipSuccess) e = launch_response(1, ctx->md, ctx->g, ctx->wk, s);
     if (e == hipSuccess) e = launch_spline(1, ctx->md, ctx->g, ctx->wk, s);
     if (e == hipSuccess) e = launch_walker_bands(1, ctx->md, ctx->g, ctx->wk, s);
@@ -466,6 +568,7 @@ mbh_status mbh_set_sparse(mbh_ctx *ctx, int B, const int64_t *band_host, const d
     if (e == hipSuccess)
         e = hipMemcpy(ctx->wk.fn, fn_host, sizeof(double) * B * nm * kNumFn * ns, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_spline(B, ctx->md, ctx->g, ctx->wk, s);
+    if (e == hipSuccess) e = launch_coef32(B, ctx->md, ctx->g, ctx->wk, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(ctx, e, "set_sparse");
     ctx->last_B = B;

@@ -20,12 +20,6 @@
 namespace mbh {
 namespace {
 
-constexpr double kInvTwoPi = 0.15915494309189533576888;
-// 2 pi = kTwoPiHi + kTwoPiLo (kTwoPiHi = 2 pi rounded to double).  With
-// fused multiply-adds, phi - n kTwoPiHi - n kTwoPiLo is accurate to a few
-// 1e-16 rad for the |n| < 2^23 of phases below ~5e7 rad.
-constexpr double kTwoPiHi = 6.283185307179586232;
-constexpr double kTwoPiLo = 2.4492935982947064e-16;
 
 // ---------------------------------------------------------------------------
 // Setup: w = 4 df / S and per-channel prefix sums of |d|^2 w.
@@ -35,7 +29,8 @@ constexpr int kScanPer = 8;
 constexpr int kScanChunk = kScanThreads * kScanPer;
 
 __global__ void k_weights(const double *__restrict__ psd, const double2 *__restrict__ d, double *__restrict__ w,
-                          double *__restrict__ e2, long long total, double df4)
+                          double *__restrict__ e2, float2 *__restrict__ dw32, float *__restrict__ sw32, long long total,
+                          double df4)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
@@ -43,6 +38,14 @@ __global__ void k_weights(const double *__restrict__ psd, const double2 *__restr
     w[i] = wi;
     const double2 di = d[i];
     e2[i] = (di.x * di.x + di.y * di.y) * wi;
+    if (dw32) {
+        // whitened FP32 copies: d sqrt(w) is O(1) and sqrt(w) stays inside the
+        // FP32 range where w itself (up to ~1e44 near the arm-transfer nulls)
+        // would not
+        const double sq = sqrt(wi);
+        dw32[i] = make_float2((float)(di.x * sq), (float)(di.y * sq));
+        sw32[i] = (float)sq;
+    }
 }
 
 // Block-local inclusive scan of kScanChunk values, deterministic order.
@@ -187,118 +190,395 @@ struct DenseArgs {
     int B, nm, ns, k0, n;
     double df;
     int max_items;
+    int one_per_walker;
     const ModeBand *band;
     const WalkerBand *wband;
     const int *wbase;
     const int *item_w;
     const double *kf;
+    const int *kbin;
     const double *coef;
     const double2 *d;
     const double *w;
     double *partial;
     double2 *h;          // template output (WriteH only)
+    const double *cis_tab;
+    // FP32 dense stage
+    const float2 *dw32;
+    const float *sw32;
+    const float *coef32;
+    const float *cis32;
 };
 
-// Largest knot index i with kf[i] <= f (clamped to [0, ns-2]), starting from
-// the log-spacing estimate.
-__device__ inline int locate(const double *kf, int ns, double fs, double fe, double f)
+__device__ __forceinline__ int uni_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// e^{i phi}: phi = q pi/2 + r with |r| <= pi/4 (two-constant FMA reduction),
+// then Taylor polynomials of sin r (to r^15) and cos r (to r^16), whose
+// truncation errors are below 5e-17 on |r| <= pi/4, and the quadrant q mod 4.
+// The 17 constants come from a small device table (filled once per context)
+// read through the constant address space, so they sit in scalar registers
+// and every Horner step is one three-operand FMA; compile-time literals end
+// up in vector registers, copied before each accumulate-form FMA.
+constexpr int kCisN = 17;
+const double kCisHost[kCisN] = {
+    0.63661977236758134308,        // 2/pi
+    1.5707963267948965580,         // pi/2 rounded to double
+    6.123233995736766036e-17,      // pi/2 - the above
+    -1.0 / 1307674368000.0, 1.0 / 6227020800.0, -1.0 / 39916800.0, 1.0 / 362880.0,
+    -1.0 / 5040.0, 1.0 / 120.0, -1.0 / 6.0,                                   // sin: r^15 .. r^3
+    1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0, -1.0 / 3628800.0,
+    1.0 / 40320.0, -1.0 / 720.0, 1.0 / 24.0};                                 // cos: r^16 .. r^4
+
+typedef const __attribute__((address_space(4))) double cdouble;
+typedef const __attribute__((address_space(4))) int cint;
+
+struct CisConst {
+    double k[kCisN];
+};
+
+__device__ __forceinline__ void load_cis(CisConst &K, const double *tab)
 {
-    int i = (int)floor(log(f / fs) / log(fe / fs) * (double)(ns - 1));
-    i = max(0, min(ns - 2, i));
-    while (i > 0 && kf[i] > f) --i;
-    while (i < ns - 2 && kf[i + 1] <= f) ++i;
-    return i;
+    cdouble *t = (cdouble *)tab;
+#pragma unroll
+    for (int i = 0; i < kCisN; ++i) K.k[i] = t[i];
 }
 
-__device__ inline double horner(const double *c, double x) { return c[0] + x * (c[1] + x * (c[2] + x * c[3])); }
-
-// e^{i phi} with the phase first reduced to [-pi, pi].
-__device__ inline void cis_reduced(double phi, double &s, double &c)
+__device__ __forceinline__ void cis(const CisConst &K, double phi, double &sn, double &cs)
 {
-    const double nq = rint(phi * kInvTwoPi);
-    double r = fma(-nq, kTwoPiHi, phi);
-    r = fma(-nq, kTwoPiLo, r);
-    sincos(r, &s, &c);
+    const double q = rint(phi * K.k[0]);
+    double r = fma(-q, K.k[1], phi);
+    r = fma(-q, K.k[2], r);
+    const double r2 = r * r;
+    double ps = fma(K.k[3], r2, K.k[4]);
+#pragma unroll
+    for (int i = 5; i <= 9; ++i) ps = fma(ps, r2, K.k[i]);
+    const double sr = fma(r * r2, ps, r);
+    double pc = fma(K.k[10], r2, K.k[11]);
+#pragma unroll
+    for (int i = 12; i <= 16; ++i) pc = fma(pc, r2, K.k[i]);
+    pc = fma(pc, r2, -0.5);
+    const double cr = fma(r2, pc, 1.0);
+    const int iq = ((int)q) & 3;
+    const double a = (iq & 1) ? cr : sr;   // sin for even q, cos for odd q
+    const double b = (iq & 1) ? sr : cr;
+    sn = (iq & 2) ? -a : a;
+    cs = ((iq + 1) & 2) ? -b : b;
 }
 
-template <bool kWriteH>
+// Cubic c0 + c1 x + c2 x^2 + c3 x^3.  From a wave-uniform table (scalar
+// registers) the first step is a multiply, because a VALU instruction reads
+// at most one scalar operand, and x enters as |x|: x = f - f_i >= 0 inside
+// interval i (the integer bin bounds guarantee k df >= f_i), and the |.|
+// source modifier makes the compiler emit the three-operand FMA that reads
+// the scalar coefficient in place instead of copying it into vector
+// registers for the two-operand accumulate form.  From per-lane registers
+// it is plain Horner.
+__device__ __forceinline__ double cubic_s(cdouble *c, double x)
+{
+    const double ax = fabs(x);
+    double p = c[3] * ax;
+    p = fma(p, ax, c[2]);
+    p = fma(p, ax, c[1]);
+    return fma(p, ax, c[0]);
+}
+__device__ __forceinline__ double cubic_v(const double *c, double x)
+{
+    return fma(fma(fma(c[3], x, c[2]), x, c[1]), x, c[0]);
+}
+
+// One mode at one bin: h^c += T^c(dx) A(dx) e^{i phi(dx)}, with the 32
+// coefficients of the bin's interval at c (A, phi, Re/Im T^A, T^E, T^T),
+// either wave-uniform (cdouble*, scalar loads) or per lane.  The compiler
+// barriers keep one group of eight coefficients in flight at a time, which
+// bounds scalar-register pressure.
+template <typename P>
+__device__ __forceinline__ double cub(P c, double x);
+template <>
+__device__ __forceinline__ double cub<cdouble *>(cdouble *c, double x) { return cubic_s(c, x); }
+template <>
+__device__ __forceinline__ double cub<const double *>(const double *c, double x) { return cubic_v(c, x); }
+
+template <typename P>
+__device__ __forceinline__ void mode_bin(const CisConst &K, P c, double dx, double (&hr)[3], double (&hi)[3])
+{
+    const double amp = cub<P>(c + 0, dx);
+    const double ph = cub<P>(c + 4, dx);
+    asm volatile("" ::: "memory");
+    double sn, cs;
+    cis(K, ph, sn, cs);
+    const double ar = amp * cs, ai = amp * sn;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const double tr = cub<P>(c + 8 + 8 * ch, dx);
+        const double ti = cub<P>(c + 12 + 8 * ch, dx);
+        hr[ch] = fma(tr, ar, fma(-ti, ai, hr[ch]));
+        hi[ch] = fma(tr, ai, fma(ti, ar, hi[ch]));
+        asm volatile("" ::: "memory");
+    }
+}
+
+// ---- FP32 dense stage ---------------------------------------------------
+// The phase polynomial is evaluated and reduced in FP64 (phases reach 1e7
+// rad); the remainder of a quarter turn, |r| <= pi/4, goes to FP32 for the
+// sine and cosine.  Amplitude and response cubics and the complex products
+// run in FP32 from an FP32 copy of the coefficients.
+constexpr int kCis32N = 10;
+const float kCis32Host[kCis32N] = {
+    1.5707963267948966f,                                                  // pi/2
+    1.0f / 362880.0f, -1.0f / 5040.0f, 1.0f / 120.0f, -1.0f / 6.0f,          // sin: r^9 .. r^3
+    -1.0f / 3628800.0f, 1.0f / 40320.0f, -1.0f / 720.0f, 1.0f / 24.0f, -0.5f  // cos: r^10 .. r^2
+};
+typedef const __attribute__((address_space(4))) float cfloat;
+
+struct CisConst32 {
+    float k[kCis32N];
+};
+
+__device__ __forceinline__ void load_cis32(CisConst32 &K, const float *tab)
+{
+    cfloat *t = (cfloat *)tab;
+#pragma unroll
+    for (int i = 0; i < kCis32N; ++i) K.k[i] = t[i];
+}
+
+// e^{i phi} for an FP64 phase: quarter turns t = phi 2/pi and q = rint(t) in
+// FP64, r = (t - q) pi/2 in FP32, Taylor polynomials of sin r (to r^9) and
+// cos r (to r^10), truncation below 2e-9 on |r| <= pi/4.
+__device__ __forceinline__ void cis32(const CisConst &K, const CisConst32 &Kf, double phi, float &sn, float &cs)
+{
+    const double t = phi * K.k[0];
+    const double q = rint(t);
+    const float r = (float)(t - q) * Kf.k[0];
+    const float r2 = r * r;
+    float ps = fmaf(Kf.k[1], r2, Kf.k[2]);
+    ps = fmaf(ps, r2, Kf.k[3]);
+    ps = fmaf(ps, r2, Kf.k[4]);
+    const float sr = fmaf(r * r2, ps, r);
+    float pc = fmaf(Kf.k[5], r2, Kf.k[6]);
+    pc = fmaf(pc, r2, Kf.k[7]);
+    pc = fmaf(pc, r2, Kf.k[8]);
+    pc = fmaf(pc, r2, Kf.k[9]);
+    const float cr = fmaf(r2, pc, 1.0f);
+    const int iq = ((int)q) & 3;
+    const float a = (iq & 1) ? cr : sr;
+    const float b = (iq & 1) ? sr : cr;
+    sn = (iq & 2) ? -a : a;
+    cs = ((iq + 1) & 2) ? -b : b;
+}
+
+__device__ __forceinline__ float cubic32_s(cfloat *c, float x)
+{
+    const float ax = fabsf(x);
+    float p = c[3] * ax;
+    p = fmaf(p, ax, c[2]);
+    p = fmaf(p, ax, c[1]);
+    return fmaf(p, ax, c[0]);
+}
+__device__ __forceinline__ float cubic32_v(const float *c, float x)
+{
+    return fmaf(fmaf(fmaf(c[3], x, c[2]), x, c[1]), x, c[0]);
+}
+template <typename P>
+__device__ __forceinline__ float cub32(P c, float x);
+template <>
+__device__ __forceinline__ float cub32<cfloat *>(cfloat *c, float x) { return cubic32_s(c, x); }
+template <>
+__device__ __forceinline__ float cub32<const float *>(const float *c, float x) { return cubic32_v(c, x); }
+
+// One mode at one bin, FP32 stage: cd points at the FP64 coefficients of the
+// interval (phase at +4), cf at their FP32 copy (amplitude at +0, response at
+// +8).
+template <typename PD, typename PF>
+__device__ __forceinline__ void mode_bin32(const CisConst &K, const CisConst32 &Kf, PD cd, PF cf, double dx,
+                                           float (&hr)[3], float (&hi)[3])
+{
+    const double ph = cub<PD>(cd + 4, dx);
+    const float dxf = (float)dx;
+    const float amp = cub32<PF>(cf + 0, dxf);
+    asm volatile("" ::: "memory");
+    float sn, cs;
+    cis32(K, Kf, ph, sn, cs);
+    const float ar = amp * cs, ai = amp * sn;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const float tr = cub32<PF>(cf + 8 + 8 * ch, dxf);
+        const float ti = cub32<PF>(cf + 12 + 8 * ch, dxf);
+        hr[ch] = fmaf(tr, ar, fmaf(-ti, ai, hr[ch]));
+        hi[ch] = fmaf(tr, ai, fmaf(ti, ar, hi[ch]));
+    }
+}
+
+// Kahan-compensated FP32 sum: s + c carries the running total.
+__device__ __forceinline__ void kahan_add(float &s, float &c, float x)
+{
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// A work item is (walker, tile); each of the four wavefronts of a block takes
+// 64*J consecutive bins in J steps of 64 (lane l: bin s_j + l).  Per step the
+// wavefront evaluates all modes at its 64 bins.  For every mode it keeps, in
+// scalar registers, the sparse interval of its current step and the first
+// bin of the next interval (integer bin bounds from kbin).  A step inside one
+// interval (the common case: intervals span tens to tens of thousands of
+// bins) reads the interval's 32 coefficients with scalar loads; a step that
+// crosses knots falls back to a per-lane interval search and per-lane loads.
+// Only the current bin's template lives in registers; the residual sums are
+// accumulated per step.
+//
+// kF32 selects the FP32 stage: whitened FP32 data, FP32 template, and
+// Kahan-compensated FP32 sums of <d|h> and <h|h> (the residual is formed in
+// the reduction from the FP64 <d|d>).
+template <bool kWriteH, bool kF32>
 __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs a)
 {
     __shared__ double red[kDenseThreads / 64][kPartials];
     const int total = min(a.wbase[a.B], a.max_items);
-    const int tid = threadIdx.x;
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int wk = a.item_w[item];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ns = a.ns;
+    CisConst K;
+    load_cis(K, a.cis_tab);
+    CisConst32 Kf;
+    if (kF32) load_cis32(Kf, a.cis32);
+    int item = blockIdx.x, end = total, step = gridDim.x;
+    if (a.one_per_walker) {
+        item = a.wbase[blockIdx.x];
+        end = min(a.wbase[blockIdx.x + 1], total);
+        step = 1;
+    }
+    for (; item < end; item += step) {
+        const int wk = uni_i(a.item_w[item]);
         const WalkerBand wb = a.wband[wk];
         const int tile = wb.tile_lo + (item - a.wbase[wk]);
-        const int kb = a.k0 + tile * kTileBins;
+        const int kw = uni_i(a.k0 + tile * kTileBins + wave * (64 * kDenseJ));
+        const int kwl = kw + 64 * kDenseJ - 1;
 
-        double hr[kDenseJ][3], hi[kDenseJ][3];
+        // per-mode wave-uniform state: band, current interval, next bound
+        int mlo[kMaxModes], mhi[kMaxModes], cur[kMaxModes], nxt[kMaxModes];
 #pragma unroll
-        for (int j = 0; j < kDenseJ; ++j)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) hr[j][c] = hi[j][c] = 0.0;
-
-        for (int im = 0; im < a.nm; ++im) {
-            const ModeBand mb = a.band[wk * a.nm + im];
-            if (!mb.active || mb.khi < kb || mb.klo >= kb + kTileBins) continue;
-            const double *kf = a.kf + (size_t)(wk * a.nm + im) * a.ns;
-            const double *cf = a.coef + (size_t)(wk * a.nm + im) * (a.ns - 1) * kCoefPerIv;
-            int iv = -1;
-#pragma unroll
-            for (int j = 0; j < kDenseJ; ++j) {
-                const int k = kb + tid + kDenseThreads * j;
-                if (k < mb.klo || k > mb.khi) continue;
-                const double f = (double)k * a.df;
-                if (iv < 0) iv = locate(kf, a.ns, mb.fs, mb.fe, f);
-                else while (iv < a.ns - 2 && kf[iv + 1] <= f) ++iv;
-                const double dx = f - kf[iv];
-                const double *c = cf + (size_t)iv * kCoefPerIv;
-                const double amp = horner(c + 0, dx);
-                const double ph = horner(c + 4, dx);
-                double sn, cs;
-                cis_reduced(ph, sn, cs);
-                const double ar = amp * cs, ai = amp * sn;
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    const double tr = horner(c + 8 + 8 * ch, dx);
-                    const double ti = horner(c + 12 + 8 * ch, dx);
-                    hr[j][ch] += tr * ar - ti * ai;
-                    hi[j][ch] += tr * ai + ti * ar;
+        for (int m = 0; m < kMaxModes; ++m) {
+            mlo[m] = 1;
+            mhi[m] = 0;
+            cur[m] = 0;
+            nxt[m] = 0x7fffffff;
+            if (m < a.nm) {
+                const ModeBand mb = a.band[wk * a.nm + m];
+                if (mb.active && mb.khi >= kw && mb.klo <= kwl) {
+                    cint *kb = (cint *)(a.kbin + (size_t)(wk * a.nm + m) * ns);
+                    const int kfirst = max(kw, mb.klo);
+                    const double f = (double)kfirst * a.df;
+                    int i = (int)floor(log(f / mb.fs) / log(mb.fe / mb.fs) * (double)(ns - 1));
+                    i = uni_i(max(0, min(ns - 2, i)));
+                    while (i > 0 && kb[i] > kfirst) i = uni_i(i - 1);
+                    while (i < ns - 2 && kb[i + 1] <= kfirst) i = uni_i(i + 1);
+                    mlo[m] = uni_i(mb.klo);
+                    mhi[m] = uni_i(mb.khi);
+                    cur[m] = i;
+                    nxt[m] = uni_i(i < ns - 2 ? kb[i + 1] : 0x7fffffff);
                 }
             }
-        }
-
-        if (kWriteH) {
-#pragma unroll
-            for (int j = 0; j < kDenseJ; ++j) {
-                const int k = kb + tid + kDenseThreads * j;
-                if (k < wb.klo || k > wb.khi) continue;
-                const int idx = k - a.k0;
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) a.h[(size_t)ch * a.n + idx] = make_double2(hr[j][ch], hi[j][ch]);
-            }
-            continue;
         }
 
         double acc[kPartials];
 #pragma unroll
         for (int q = 0; q < kPartials; ++q) acc[q] = 0.0;
+        float ks[6], kc[6];   // FP32 stage: Kahan sums of DH_c, HH_c
 #pragma unroll
+        for (int q = 0; q < 6; ++q) ks[q] = kc[q] = 0.0f;
+
         for (int j = 0; j < kDenseJ; ++j) {
-            const int k = kb + tid + kDenseThreads * j;
-            if (k < wb.klo || k > wb.khi) continue;
-            const int idx = k - a.k0;
+            const int s0 = kw + 64 * j;
+            const int k = s0 + lane;
+            const bool inw = (k >= wb.klo) && (k <= wb.khi);
+            const int idx = inw ? k - a.k0 : 0;
+            double2 dv[3];
+            double wv[3];
+            float2 dv32[3];
+            float sv32[3];
+            if (!kWriteH && !kF32) {
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const double2 dv = a.d[(size_t)ch * a.n + idx];
-                const double wv = a.w[(size_t)ch * a.n + idx];
-                const double rr = dv.x - hr[j][ch], ri = dv.y - hi[j][ch];
-                acc[ch] += (rr * rr + ri * ri) * wv;
-                acc[3 + ch] += (dv.x * hr[j][ch] + dv.y * hi[j][ch]) * wv;
-                acc[6 + ch] += (hr[j][ch] * hr[j][ch] + hi[j][ch] * hi[j][ch]) * wv;
+                for (int ch = 0; ch < 3; ++ch) {
+                    dv[ch] = a.d[(size_t)ch * a.n + idx];
+                    wv[ch] = a.w[(size_t)ch * a.n + idx];
+                }
+            }
+            if (!kWriteH && kF32) {
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    dv32[ch] = a.dw32[(size_t)ch * a.n + idx];
+                    sv32[ch] = a.sw32[(size_t)ch * a.n + idx];
+                }
+            }
+            const double f = (double)k * a.df;
+            double hr[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+            float hr32[3] = {0.0f, 0.0f, 0.0f}, hi32[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int m = 0; m < kMaxModes; ++m) {
+                const int lo = max(s0, mlo[m]), hi_ = min(s0 + 63, mhi[m]);
+                if (lo > hi_) continue;
+                const size_t wm = (size_t)(wk * a.nm + m);
+                const int *kb = a.kbin + wm * ns;
+                const double *kf = a.kf + wm * ns;
+                const double *cf = a.coef + wm * (ns - 1) * kCoefPerIv;
+                while (nxt[m] <= lo) {
+                    cur[m] = uni_i(cur[m] + 1);
+                    nxt[m] = uni_i(cur[m] < ns - 2 ? ((cint *)kb)[cur[m] + 1] : 0x7fffffff);
+                }
+                const bool in = (k >= mlo[m]) && (k <= mhi[m]);
+                const float *cf32 = kF32 ? a.coef32 + wm * (ns - 1) * kCoefPerIv : nullptr;
+                if (hi_ < nxt[m]) {
+                    const int iv = cur[m];
+                    const double x0 = ((cdouble *)kf)[iv];
+                    if (in) {
+                        if (kF32)
+                            mode_bin32<cdouble *, cfloat *>(K, Kf, (cdouble *)(cf + (size_t)iv * kCoefPerIv),
+                                                            (cfloat *)(cf32 + (size_t)iv * kCoefPerIv), f - x0, hr32,
+                                                            hi32);
+                        else
+                            mode_bin<cdouble *>(K, (cdouble *)(cf + (size_t)iv * kCoefPerIv), f - x0, hr, hi);
+                    }
+                } else if (in) {
+                    int iv = cur[m];
+                    while (iv < ns - 2 && kb[iv + 1] <= k) ++iv;
+                    if (kF32)
+                        mode_bin32<const double *, const float *>(K, Kf, cf + (size_t)iv * kCoefPerIv,
+                                                                  cf32 + (size_t)iv * kCoefPerIv, f - kf[iv], hr32,
+                                                                  hi32);
+                    else
+                        mode_bin<const double *>(K, cf + (size_t)iv * kCoefPerIv, f - kf[iv], hr, hi);
+                }
+            }
+            if (kWriteH) {
+                if (inw)
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) a.h[(size_t)ch * a.n + idx] = make_double2(hr[ch], hi[ch]);
+            } else if (kF32) {
+                if (inw) {
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) {
+                        const float wr = hr32[ch] * sv32[ch], wi = hi32[ch] * sv32[ch];
+                        kahan_add(ks[ch], kc[ch], fmaf(dv32[ch].x, wr, dv32[ch].y * wi));
+                        kahan_add(ks[3 + ch], kc[3 + ch], fmaf(wr, wr, wi * wi));
+                    }
+                }
+            } else if (inw) {
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const double rr = dv[ch].x - hr[ch], ri = dv[ch].y - hi[ch];
+                    acc[ch] = fma(fma(rr, rr, ri * ri), wv[ch], acc[ch]);
+                    acc[3 + ch] = fma(fma(dv[ch].x, hr[ch], dv[ch].y * hi[ch]), wv[ch], acc[3 + ch]);
+                    acc[6 + ch] = fma(fma(hr[ch], hr[ch], hi[ch] * hi[ch]), wv[ch], acc[6 + ch]);
+                }
             }
         }
+        if (kWriteH) continue;
+        if (kF32) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) acc[3 + q] = (double)ks[q] - (double)kc[q];
+        }
+
         // wavefront butterfly, then the four wavefronts in order
 #pragma unroll
         for (int q = 0; q < kPartials; ++q) {
@@ -307,16 +587,15 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs a)
             for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
             acc[q] = v;
         }
-        const int wave = tid >> 6, lane = tid & 63;
         if (lane == 0)
 #pragma unroll
             for (int q = 0; q < kPartials; ++q) red[wave][q] = acc[q];
         __syncthreads();
-        if (tid < kPartials) {
+        if (threadIdx.x < kPartials) {
             double s = 0.0;
 #pragma unroll
-            for (int wv = 0; wv < kDenseThreads / 64; ++wv) s += red[wv][tid];
-            a.partial[(size_t)item * kPartials + tid] = s;
+            for (int wv = 0; wv < kDenseThreads / 64; ++wv) s += red[wv][threadIdx.x];
+            a.partial[(size_t)item * kPartials + threadIdx.x] = s;
         }
         __syncthreads();
     }
@@ -348,13 +627,26 @@ __global__ void k_reduce(int B, GridDesc g, const Source *__restrict__ src, cons
         for (int q = 1; q < 7; ++q) o[q] = 0.0;
     } else {
         const WalkerBand wb = wband[w];
-        double dd_out = 0.0;
-        for (int c = 0; c < 3; ++c) {
-            const double *p = pre + (size_t)c * (g.n + 1);
-            if (wb.ntiles > 0) dd_out += p[wb.klo - g.k0] + (p[g.n] - p[wb.khi - g.k0 + 1]);
-            else dd_out += p[g.n];
+        if (g.precision == 0) {
+            // residual form over the band, data-only sum outside it
+            double dd_out = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double *p = pre + (size_t)c * (g.n + 1);
+                if (wb.ntiles > 0) dd_out += p[wb.klo - g.k0] + (p[g.n] - p[wb.khi - g.k0 + 1]);
+                else dd_out += p[g.n];
+            }
+            o[0] = -0.5 * (acc[0] + acc[1] + acc[2] + dd_out);
+        } else {
+            // FP32 stage: <d|d> in FP64 from the prefix sums, <d|h> and <h|h>
+            // from the compensated FP32 sums
+            double dd = 0.0, dh = 0.0, hh = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                dd += pre[(size_t)c * (g.n + 1) + g.n];
+                dh += acc[3 + c];
+                hh += acc[6 + c];
+            }
+            o[0] = -0.5 * (dd + hh - 2.0 * dh);
         }
-        o[0] = -0.5 * (acc[0] + acc[1] + acc[2] + dd_out);
         for (int c = 0; c < 3; ++c) {
             o[1 + c] = acc[3 + c];
             o[4 + c] = acc[6 + c];
@@ -375,41 +667,82 @@ DenseArgs make_args(int B, const Modes &md, const GridDesc &g, const Work &wk, c
     a.n = g.n;
     a.df = g.df;
     a.max_items = max_items;
+    a.one_per_walker = 0;
     a.band = wk.band;
     a.wband = wk.wband;
     a.wbase = wk.wbase;
     a.item_w = wk.item_w;
     a.kf = wk.kf;
+    a.kbin = wk.kbin;
     a.coef = wk.coef;
     a.d = dt.d;
     a.w = dt.w;
     a.partial = wk.partial;
     a.h = nullptr;
+    a.cis_tab = wk.cis_tab;
+    a.dw32 = dt.dw32;
+    a.sw32 = dt.sw32;
+    a.coef32 = wk.coef32;
+    a.cis32 = wk.cis32;
     return a;
 }
 
-int dense_grid()
+int num_cus()
 {
-    static int grid = 0;
-    if (grid == 0) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-        grid = cus * 8;
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, c = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+            c = 256;
+        cus = c;
     }
-    return grid;
+    return cus;
+}
+
+int dense_grid(int B, const Schedule &sch)
+{
+    if (sch.one_per_walker) return B;
+    return num_cus() * sch.blocks_per_cu;
+}
+
+// FP32 copy of the spline coefficient table
+__global__ void k_coef32(const double *__restrict__ coef, float *__restrict__ coef32, long long total)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < total) coef32[i] = (float)coef[i];
 }
 
 }  // namespace
 
+const double *cis_table_host(int *n)
+{
+    *n = kCisN;
+    return kCisHost;
+}
+
+const float *cis32_table_host(int *n)
+{
+    *n = kCis32N;
+    return kCis32Host;
+}
+
+hipError_t launch_coef32(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st)
+{
+    if (B <= 0 || g.precision == 0) return hipSuccess;
+    const long long total = (long long)B * md.nm * (g.ns - 1) * kCoefPerIv;
+    k_coef32<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(wk.coef, wk.coef32, total);
+    return hipGetLastError();
+}
+
 hipError_t launch_setup_data(const double *psd, const double2 *d, double *w, double *pre, double *scratch,
-                             const GridDesc &g, double df4, hipStream_t st)
+                             float2 *dw32, float *sw32, const GridDesc &g, double df4, hipStream_t st)
 {
     const long long total = 3LL * g.n;
     double *e2 = scratch;                  // [3][n]
     const int nchunks = (g.n + kScanChunk - 1) / kScanChunk;
     double *chunk = scratch + total;       // [3][nchunks]
-    k_weights<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(psd, d, w, e2, total, df4);
+    k_weights<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(psd, d, w, e2, dw32, sw32, total, df4);
     k_scan_chunks<<<dim3(nchunks, 3), kScanThreads, 0, st>>>(e2, g.n, chunk, nchunks);
     k_scan_offsets<<<3, kScanThreads, 0, st>>>(chunk, nchunks);
     k_scan_final<<<dim3(nchunks, 3), kScanThreads, 0, st>>>(e2, g.n, chunk, nchunks, pre);
@@ -425,14 +758,19 @@ hipError_t launch_walker_bands(int B, const Modes &md, const GridDesc &g, const 
 }
 
 hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &wk, const Data &dt, int max_items,
-                        hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
+                        const Schedule &sch, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (B <= 0) return hipSuccess;
     k_fill_items<<<B, 256, 0, st>>>(B, wk.wband, wk.wbase, wk.item_w, max_items);
     DenseArgs a = make_args(B, md, g, wk, dt, max_items);
+    a.one_per_walker = sch.one_per_walker;
+    const int grid = dense_grid(B, sch);
     hipError_t e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
-    k_dense<false><<<dense_grid(), kDenseThreads, 0, st>>>(a);
+    if (g.precision == 0)
+        k_dense<false, false><<<grid, kDenseThreads, 0, st>>>(a);
+    else
+        k_dense<false, true><<<grid, kDenseThreads, 0, st>>>(a);
     if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -445,14 +783,24 @@ hipError_t launch_reduce(int B, const GridDesc &g, const Work &wk, const Data &d
     return hipGetLastError();
 }
 
+// Zero fill by a kernel rather than a memset node, so that a caller may
+// capture the template launch in a graph.
+__global__ void k_zero2(double2 *__restrict__ h, long long count)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) h[i] = make_double2(0.0, 0.0);
+}
+
 hipError_t launch_template(const Modes &md, const GridDesc &g, const Work &wk, double2 *h, hipStream_t st)
 {
-    Data none = {nullptr, nullptr, nullptr};
+    Data none = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    const long long nh = 3LL * g.n;
+    k_zero2<<<(unsigned)((nh + 255) / 256), 256, 0, st>>>(h, nh);
     const int max_items = (g.n + kTileBins - 1) / kTileBins + 1;
     k_fill_items<<<1, 256, 0, st>>>(1, wk.wband, wk.wbase, wk.item_w, max_items);
     DenseArgs a = make_args(1, md, g, wk, none, max_items);
     a.h = h;
-    k_dense<true><<<dense_grid(), kDenseThreads, 0, st>>>(a);
+    k_dense<true, false><<<dense_grid(1, Schedule()), kDenseThreads, 0, st>>>(a);
     return hipGetLastError();
 }
 

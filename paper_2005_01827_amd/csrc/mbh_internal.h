@@ -14,10 +14,11 @@ constexpr int kNumFn = 8;          // A, phi, Re/Im T^A, Re/Im T^E, Re/Im T^T
 constexpr int kCoefPerIv = kNumFn * 4;  // 32 doubles per sparse interval
 
 // Dense tiling of the frequency axis: a work item is (walker, tile) with
-// kTileBins consecutive bins, processed by kDenseThreads threads that each
-// take kDenseJ bins strided by kDenseThreads (coalesced loads of d and w).
+// kTileBins consecutive bins, processed by kDenseThreads threads; each
+// wavefront takes 64*kDenseJ consecutive bins in kDenseJ steps of 64
+// (coalesced loads of d and w).
 constexpr int kDenseThreads = 256;
-constexpr int kDenseJ = 4;
+constexpr int kDenseJ = 8;
 constexpr int kTileBins = kDenseThreads * kDenseJ;
 constexpr int kPartials = 9;       // R_c, DH_c, HH_c for c = A, E, T
 
@@ -62,6 +63,7 @@ struct GridDesc {
     int k0;
     int n;
     int ns;             // sparse knots per mode
+    int precision;      // 0: FP64 dense stage; 1: FP32 with compensated sums
 };
 
 // Device workspace of a context (all pointers device memory).
@@ -74,10 +76,14 @@ struct Work {
     double *fn;             // [B][nm][8][ns]     function values at the knots
     double *coef;           // [B][nm][ns-1][8][4] spline coefficients
     double *spline_scratch; // [B][nm][8][2 ns]
+    int *kbin;              // [B][nm][ns] first dense bin k with k df >= knot
     int *item_w;            // [max items] walker of each work item
     int *wbase;             // [B+1]  exclusive scan of ntiles; wbase[B] = total
     double *partial;        // [max items][9]
     double *out7;           // [B][7] default output
+    double *cis_tab;        // constants of the dense-stage sin/cos
+    float *cis32;           // the same for the FP32 dense stage
+    float *coef32;          // [B][nm][ns-1][32] FP32 copy of coef (FP32 dense stage)
 };
 
 // Data resident for the life of a context.
@@ -85,11 +91,22 @@ struct Data {
     const double2 *d;       // [3][n]   A, E, T data
     const double *w;        // [3][n]   4 df / S_n
     const double *pre;      // [3][n+1] prefix sums of |d|^2 w
+    const float2 *dw32;     // [3][n]   d sqrt(w) in FP32 (FP32 dense stage)
+    const float *sw32;      // [3][n]   sqrt(w) in FP32
 };
 
 // ---- launchers (each defined next to its kernels) ----
+// host copies of the dense-stage sin/cos constants (uploaded to Work::cis_tab
+// and Work::cis32)
+const double *cis_table_host(int *n);
+const float *cis32_table_host(int *n);
+
+// dw32 / sw32 may be null (FP64 contexts)
 hipError_t launch_setup_data(const double *psd, const double2 *d, double *w, double *pre, double *scratch,
-                             const GridDesc &g, double df4, hipStream_t st);
+                             float2 *dw32, float *sw32, const GridDesc &g, double df4, hipStream_t st);
+
+// FP32 copy of the spline coefficients for the FP32 dense stage
+hipError_t launch_coef32(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st);
 
 hipError_t launch_waveform(const double *params, int B, const Modes &md, const GridDesc &g, const Work &wk,
                            hipStream_t st);
@@ -100,9 +117,21 @@ hipError_t launch_spline(int B, const Modes &md, const GridDesc &g, const Work &
 
 hipError_t launch_walker_bands(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st);
 
+// Launch shape of the dense kernel: blocks_per_cu workgroups per compute unit
+// in a grid-stride loop over the (walker, tile) items, or, with
+// one_per_walker, one workgroup per walker walking its own tiles (the
+// unbalanced reference schedule).
+struct Schedule {
+    int blocks_per_cu = 8;
+    int one_per_walker = 0;
+};
+
+int num_cus();
+
 // ev0/ev1 (optional) are recorded on st right before and after the dense kernel.
 hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &wk, const Data &dt,
-                        int max_items, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                        int max_items, const Schedule &sch, hipStream_t st, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
 
 hipError_t launch_reduce(int B, const GridDesc &g, const Work &wk, const Data &dt, double *out7,
                          double *logL, hipStream_t st);

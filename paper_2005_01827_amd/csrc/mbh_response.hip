@@ -147,10 +147,14 @@ __global__ void k_response(int B, Modes md, GridDesc g, const Source *__restrict
 // One thread per (walker, mode, function): not-a-knot spline through
 // (f_j, y_j).  Unknowns M_1..M_{ns-2} (second derivatives); M_0 and M_{ns-1}
 // follow from continuity of the third derivative at f_1 and f_{ns-2}.
-// scratch holds 2*ns doubles per thread.
+// scratch holds 2*ns doubles per thread.  The q = 0 thread of each
+// (walker, mode) also writes kbin[i], the first dense bin k with
+// k df >= f_i, so that the dense stage can find intervals by integer
+// comparison: bin k lies in interval i iff kbin[i] <= k < kbin[i+1], which
+// is the same as f_i <= k df < f_{i+1} in double precision.
 __global__ void k_spline(int B, Modes md, GridDesc g, const ModeBand *__restrict__ band,
                          const double *__restrict__ kf, const double *__restrict__ fn, double *__restrict__ coef,
-                         double *__restrict__ scratch)
+                         double *__restrict__ scratch, int *__restrict__ kbin)
 {
     const int ns = g.ns;
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -158,6 +162,19 @@ __global__ void k_spline(int B, Modes md, GridDesc g, const ModeBand *__restrict
     const int q = id % kNumFn;
     const int wm = id / kNumFn;
     double *out = coef + (size_t)wm * (ns - 1) * kCoefPerIv + q * 4;
+    if (q == 0) {
+        const double *x = kf + (size_t)wm * ns;
+        int *kb = kbin + (size_t)wm * ns;
+        const bool act = band[wm].active != 0;
+        for (int i = 0; i < ns; ++i) {
+            long long k = act ? (long long)ceil(x[i] / g.df) : 0;
+            if (act) {
+                while ((double)k * g.df < x[i]) ++k;
+                while ((double)(k - 1) * g.df >= x[i]) --k;
+            }
+            kb[i] = (int)max(-1LL, min(k, 0x7ffffffeLL));
+        }
+    }
     if (!band[wm].active) {
         for (int i = 0; i < ns - 1; ++i)
             for (int c = 0; c < 4; ++c) out[(size_t)i * kCoefPerIv + c] = 0.0;
@@ -228,7 +245,7 @@ hipError_t launch_spline(int B, const Modes &md, const GridDesc &g, const Work &
 {
     if (B <= 0) return hipSuccess;
     const int nt = B * md.nm * kNumFn;
-    k_spline<<<(nt + 63) / 64, 64, 0, st>>>(B, md, g, wk.band, wk.kf, wk.fn, wk.coef, wk.spline_scratch);
+    k_spline<<<(nt + 63) / 64, 64, 0, st>>>(B, md, g, wk.band, wk.kf, wk.fn, wk.coef, wk.spline_scratch, wk.kbin);
     return hipGetLastError();
 }
 

@@ -186,7 +186,7 @@ def config2(n_walkers: int = 1024) -> Workload:
     inj = np.array([3e6, 0.3, 0.3, -0.2, luminosity_distance_gpc(3.0), 2.14, 1.05, 2 * math.pi - 0.024,
                     0.62, 2.03, 50.25])
     walkers = ball(inj, n_walkers, 1e-3, 202)
-    return Workload("cfg2-1024walkers-Tobs2^25", grid, YEAR_S, inj, walkers, noise_seed=2002)
+    return Workload(f"cfg2-{n_walkers}walkers-Tobs2^25", grid, YEAR_S, inj, walkers, noise_seed=2002)
 
 
 def config3(n_walkers: int = 2048) -> Workload:

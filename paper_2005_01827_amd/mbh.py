@@ -21,7 +21,10 @@ STATUS_NAMES = {0: "MBH_OK", -1: "MBH_EINVAL", -2: "MBH_ENOMEM", -3: "MBH_EHIP",
 # Every entry point declared in include/mbh.h.
 EXPORTED = ("mbh_ctx_create", "mbh_ctx_destroy", "mbh_last_error", "mbh_waveform_gen", "mbh_response",
             "mbh_interp_and_inner", "mbh_loglike_batch", "mbh_template", "mbh_get_sparse", "mbh_set_sparse",
-            "mbh_set_timing", "mbh_get_timing", "mbh_version")
+            "mbh_set_timing", "mbh_get_timing", "mbh_set_schedule", "mbh_get_schedule", "mbh_autotune",
+            "mbh_flow_create", "mbh_flow_destroy", "mbh_flow_last_error",
+            "mbh_flow_num_params", "mbh_flow_get_layout", "mbh_flow_get_params", "mbh_flow_set_params",
+            "mbh_flow_forward", "mbh_flow_inverse", "mbh_flow_loss_grad", "mbh_flow_adam", "mbh_version")
 
 
 class MbhError(RuntimeError):
@@ -69,6 +72,30 @@ def load_library(path: str = LIB_PATH):
     L.mbh_set_timing.restype = ctypes.c_int
     L.mbh_get_timing.argtypes = [vp, dp, i64p]
     L.mbh_get_timing.restype = ctypes.c_int
+    ip, fp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)
+    L.mbh_set_schedule.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.mbh_get_schedule.argtypes = [vp, ip, ip]
+    L.mbh_autotune.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ip, dp, vp]
+    for name in ("mbh_set_schedule", "mbh_get_schedule", "mbh_autotune"):
+        getattr(L, name).restype = ctypes.c_int
+    L.mbh_flow_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ctypes.c_uint64,
+                                  ctypes.POINTER(vp)]
+    L.mbh_flow_destroy.argtypes = [vp]
+    L.mbh_flow_destroy.restype = None
+    L.mbh_flow_last_error.argtypes = [vp]
+    L.mbh_flow_last_error.restype = ctypes.c_char_p
+    L.mbh_flow_num_params.argtypes = [vp]
+    L.mbh_flow_num_params.restype = ctypes.c_int64
+    L.mbh_flow_get_layout.argtypes = [vp, ip, ip]
+    L.mbh_flow_get_params.argtypes = [vp, fp]
+    L.mbh_flow_set_params.argtypes = [vp, fp]
+    L.mbh_flow_forward.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp]
+    L.mbh_flow_inverse.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp]
+    L.mbh_flow_loss_grad.argtypes = [vp, vp, ctypes.c_int, dp, fp, vp]
+    L.mbh_flow_adam.argtypes = [vp, ctypes.c_float, vp]
+    for name in ("mbh_flow_create", "mbh_flow_get_layout", "mbh_flow_get_params", "mbh_flow_set_params",
+                 "mbh_flow_forward", "mbh_flow_inverse", "mbh_flow_loss_grad", "mbh_flow_adam"):
+        getattr(L, name).restype = ctypes.c_int
     L.mbh_version.restype = ctypes.c_int
     _lib = L
     return L
@@ -99,6 +126,7 @@ class Likelihood:
         self.modes = tuple(tuple(m) for m in modes)
         self.n_sparse = n_sparse
         self.max_batch = max_batch
+        self.precision = precision
         d = np.ascontiguousarray(np.stack([np.asarray(data).real, np.asarray(data).imag], axis=-1), dtype=np.float64)
         S = np.ascontiguousarray(psd, dtype=np.float64)
         if d.shape != (3, grid.n, 2) or S.shape != (3, grid.n):
@@ -215,10 +243,160 @@ class Likelihood:
         self._check(self.lib.mbh_get_timing(self.ctx, ctypes.byref(ms), ctypes.byref(cnt)), "mbh_get_timing")
         return ms.value, cnt.value
 
+    def set_schedule(self, blocks_per_cu=8, one_per_walker=False):
+        self._check(self.lib.mbh_set_schedule(self.ctx, int(blocks_per_cu), 1 if one_per_walker else 0),
+                    "mbh_set_schedule")
+
+    def get_schedule(self):
+        b, o = ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.mbh_get_schedule(self.ctx, ctypes.byref(b), ctypes.byref(o)), "mbh_get_schedule")
+        return b.value, bool(o.value)
+
+    def autotune(self, params, reps=5, cache=None, key=None, stream=None):
+        """Pick the dense launch shape for this batch (see mbh_autotune).
+
+        With a cache path, results are stored as JSON under 'key' (default:
+        grid size, batch, modes, precision and the GPU name) and reused.
+        Returns (blocks_per_cu, median dense ms or None if from the cache)."""
+        import json
+        t = self._torch
+        p = self._params(params)
+        if key is None:
+            key = (f"{t.cuda.get_device_name()}|n={self.grid.n}|B={p.shape[0]}|modes={len(self.modes)}|"
+                   f"ns={self.n_sparse}|prec={self.precision}")
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                table = json.load(fh)
+        if key in table:
+            self.set_schedule(table[key]["blocks_per_cu"], False)
+            return table[key]["blocks_per_cu"], None
+        b, ms = ctypes.c_int(), ctypes.c_double()
+        self._check(self.lib.mbh_autotune(self.ctx, ctypes.c_void_p(p.data_ptr()), p.shape[0], reps,
+                                          ctypes.byref(b), ctypes.byref(ms), self._stream(stream)), "mbh_autotune")
+        if cache:
+            table[key] = {"blocks_per_cu": b.value, "dense_ms": ms.value}
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as fh:
+                json.dump(table, fh, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return b.value, ms.value
+
     def close(self):
         if getattr(self, "ctx", None):
             self.lib.mbh_ctx_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Flow:
+    """The affine-coupling flow of include/mbh.h (FP32, on the GPU).
+
+    Rows are float32 [n][dim] torch CUDA tensors (numpy arrays are copied to
+    the device).  perm: optional [L][dim] int permutations.
+    """
+
+    def __init__(self, dim, n_layers=8, hidden=128, max_batch=65536, perm=None, seed=0):
+        self._torch = _torch()
+        self.lib = load_library()
+        self.dim, self.n_layers, self.hidden, self.max_batch = dim, n_layers, hidden, max_batch
+        self._torch.cuda.init()
+        pp = None
+        if perm is not None:
+            self._perm_in = np.ascontiguousarray(perm, dtype=np.int32)
+            if self._perm_in.shape != (n_layers, dim):
+                raise ValueError("perm must be [n_layers][dim]")
+            pp = self._perm_in.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        h = ctypes.c_void_p()
+        st = self.lib.mbh_flow_create(dim, n_layers, hidden, max_batch, pp, seed, ctypes.byref(h))
+        if st != MBH_OK:
+            raise MbhError(st, "mbh_flow_create rejected the arguments or failed to allocate")
+        self.flow = h
+        self.n_params = int(self.lib.mbh_flow_num_params(h))
+
+    def _check(self, st, what):
+        if st != MBH_OK:
+            msg = self.lib.mbh_flow_last_error(self.flow)
+            raise MbhError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def _stream(self, stream=None):
+        s = stream if stream is not None else self._torch.cuda.current_stream()
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def _rows(self, x):
+        t = self._torch
+        r = x if isinstance(x, t.Tensor) else t.as_tensor(np.asarray(x, dtype=np.float32))
+        r = r.to(device="cuda", dtype=t.float32).contiguous()
+        if r.dim() != 2 or r.shape[1] != self.dim:
+            raise ValueError(f"rows must be [n][{self.dim}]")
+        return r
+
+    def layout(self):
+        perm = np.zeros((self.n_layers, self.dim), dtype=np.int32)
+        nc = np.zeros(self.n_layers, dtype=np.int32)
+        ip = ctypes.POINTER(ctypes.c_int)
+        self._check(self.lib.mbh_flow_get_layout(self.flow, perm.ctypes.data_as(ip), nc.ctypes.data_as(ip)),
+                    "mbh_flow_get_layout")
+        return perm, nc
+
+    def get_params(self):
+        p = np.empty(self.n_params, dtype=np.float32)
+        self._check(self.lib.mbh_flow_get_params(self.flow, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+                    "mbh_flow_get_params")
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.shape != (self.n_params,):
+            raise ValueError(f"expected {self.n_params} parameters")
+        self._check(self.lib.mbh_flow_set_params(self.flow, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+                    "mbh_flow_set_params")
+
+    def forward(self, u, stream=None):
+        """(z, log q(u)) as CUDA tensors."""
+        u = self._rows(u)
+        n = u.shape[0]
+        z = self._torch.empty_like(u)
+        lq = self._torch.empty(n, dtype=self._torch.float32, device="cuda")
+        self._check(self.lib.mbh_flow_forward(self.flow, ctypes.c_void_p(u.data_ptr()), n,
+                                              ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(lq.data_ptr()),
+                                              self._stream(stream)), "mbh_flow_forward")
+        return z, lq
+
+    def inverse(self, z, stream=None):
+        """(u = f^-1(z), log q(u)) as CUDA tensors."""
+        z = self._rows(z)
+        n = z.shape[0]
+        u = self._torch.empty_like(z)
+        lq = self._torch.empty(n, dtype=self._torch.float32, device="cuda")
+        self._check(self.lib.mbh_flow_inverse(self.flow, ctypes.c_void_p(z.data_ptr()), n,
+                                              ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(lq.data_ptr()),
+                                              self._stream(stream)), "mbh_flow_inverse")
+        return u, lq
+
+    def loss_grad(self, u, want_grad=True, stream=None):
+        """(loss, gradient as a float32 numpy array or None)."""
+        u = self._rows(u)
+        loss = ctypes.c_double()
+        g = np.empty(self.n_params, dtype=np.float32) if want_grad else None
+        gp = g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if want_grad else None
+        self._check(self.lib.mbh_flow_loss_grad(self.flow, ctypes.c_void_p(u.data_ptr()), u.shape[0],
+                                                ctypes.byref(loss), gp, self._stream(stream)), "mbh_flow_loss_grad")
+        return loss.value, g
+
+    def adam(self, lr, stream=None):
+        self._check(self.lib.mbh_flow_adam(self.flow, float(lr), self._stream(stream)), "mbh_flow_adam")
+
+    def close(self):
+        if getattr(self, "flow", None):
+            self.lib.mbh_flow_destroy(self.flow)
+            self.flow = None
 
     def __del__(self):
         try:

@@ -259,10 +259,14 @@ class PTSampler:
         fd, tmp = tempfile.mkstemp(dir=d, suffix=".npz")
         os.close(fd)
         import json
+        extra = {}
+        if isinstance(self.proposal, FlowProposal):
+            extra = dict(flow_params=self.proposal.flow.get_params(), flow_mu=self.proposal.mu,
+                         flow_sd=self.proposal.sd, p_flow=np.array(self.p_flow))
         np.savez(tmp, x=st.x, logl=st.logl, logp=st.logp, step=st.step, betas=self.betas,
                  accepted=st.accepted, proposed=st.proposed, swaps_accepted=st.swaps_accepted,
                  swaps_proposed=st.swaps_proposed, flow=np.array([st.flow_accepted, st.flow_proposed]),
-                 rng=np.frombuffer(json.dumps(self.rng.bit_generator.state).encode(), dtype=np.uint8))
+                 rng=np.frombuffer(json.dumps(self.rng.bit_generator.state).encode(), dtype=np.uint8), **extra)
         os.replace(tmp, path)
 
     def load(self, path: str):
@@ -271,11 +275,67 @@ class PTSampler:
         rng_state = json.loads(bytes(z["rng"]).decode())
         self.rng.bit_generator.state = rng_state
         fl = z["flow"]
+        if "flow_params" in z.files and isinstance(self.proposal, FlowProposal):
+            self.proposal.flow.set_params(z["flow_params"])
+            self.proposal.mu = z["flow_mu"].copy()
+            self.proposal.sd = z["flow_sd"].copy()
+            self.p_flow = float(z["p_flow"])
         self.state = PTState(x=z["x"].copy(), logl=z["logl"].copy(), logp=z["logp"].copy(), step=int(z["step"]),
                              rng_state=rng_state, accepted=z["accepted"].copy(), proposed=z["proposed"].copy(),
                              swaps_accepted=z["swaps_accepted"].copy(), swaps_proposed=z["swaps_proposed"].copy(),
                              flow_accepted=int(fl[0]), flow_proposed=int(fl[1]))
         return self.state
+
+
+class FlowProposal:
+    """Independence proposal from the learned affine-coupling flow (mbh.Flow).
+
+    The flow models standardized coordinates u = (x - mu) / sd, with mu and sd
+    taken from the training samples, so log q_x(x) = log q_u(u) - sum log sd.
+    Draws are u = f^{-1}(z) with z ~ N(0, I) from the sampler's generator.
+    Both densities in the acceptance ratio are evaluated by the same forward
+    pass, so q is one deterministic function of x.
+    """
+
+    def __init__(self, dim: int, n_layers: int = 8, hidden: int = 128, max_batch: int = 65536, seed: int = 0,
+                 flow=None):
+        from . import mbh
+        self.dim = dim
+        self.flow = flow if flow is not None else mbh.Flow(dim, n_layers, hidden, max_batch, seed=seed)
+        self.mu = np.zeros(dim)
+        self.sd = np.ones(dim)
+        self.losses = []
+        self.train_seconds = 0.0
+
+    def fit(self, x: np.ndarray, steps: int = 400, lr: float = 2e-3, batch: int = 4096, seed: int = 0):
+        """Adam on minibatches of the samples x [N][dim]; returns the losses."""
+        import torch
+        t0 = time.perf_counter()
+        x = np.asarray(x, dtype=np.float64).reshape(-1, self.dim)
+        self.mu = x.mean(axis=0)
+        self.sd = x.std(axis=0) + 1e-12
+        u = torch.as_tensor(((x - self.mu) / self.sd).astype(np.float32), device="cuda")
+        rng = np.random.default_rng(seed)
+        batch = min(batch, len(x), self.flow.max_batch)
+        for _ in range(steps):
+            idx = torch.as_tensor(rng.integers(0, len(x), batch), device="cuda")
+            loss, _ = self.flow.loss_grad(u.index_select(0, idx), want_grad=False)
+            self.flow.adam(lr)
+            self.losses.append(loss + float(np.sum(np.log(self.sd))))
+        torch.cuda.synchronize()
+        self.train_seconds += time.perf_counter() - t0
+        return self.losses
+
+    def logq(self, x: np.ndarray) -> np.ndarray:
+        u = (np.atleast_2d(x) - self.mu) / self.sd
+        _, lq = self.flow.forward(u.astype(np.float32))
+        return lq.cpu().numpy().astype(np.float64) - float(np.sum(np.log(self.sd)))
+
+    def sample(self, n: int, rng: np.random.Generator):
+        z = rng.standard_normal((n, self.dim)).astype(np.float32)
+        u, _ = self.flow.inverse(z)
+        x = self.mu + self.sd * u.cpu().numpy().astype(np.float64)
+        return x, self.logq(x)
 
 
 def box_logprior(lo=inputs.PRIOR_LO, hi=inputs.PRIOR_HI):
@@ -299,3 +359,93 @@ def gpu_loglike(L):
         out = L.loglike(th)
         return out.cpu().numpy()
     return f
+
+
+# ---------------------------------------------------------------------------
+# ESS per second: stretch only against stretch + learned proposal
+# ---------------------------------------------------------------------------
+def _run_for(smp: PTSampler, seconds: float, chain: list, t_start: float, say=None, every: float = 30.0):
+    last = time.perf_counter()
+    while time.perf_counter() - t_start < seconds:
+        smp.step()
+        chain.append(smp.state.x[0].copy())
+        if say is not None and time.perf_counter() - last > every:
+            last = time.perf_counter()
+            say("progress", {"steps": len(chain), "wall_s": round(last - t_start, 1)})
+
+
+def _arm_report(smp: PTSampler, chain: np.ndarray, wall: float, burn: int):
+    post = chain[burn:]
+    n_eff, tau, taus = ess(post) if len(post) >= 8 else (0.0, float("inf"), None)
+    st = smp.state
+    return {
+        "steps": int(len(chain)), "burn_in_steps": int(burn), "wall_s": round(wall, 2),
+        "like_s": round(smp.like_seconds, 2), "tau": round(float(tau), 2), "ess": round(float(n_eff), 1),
+        "ess_per_s": round(float(n_eff) / wall, 3), "chain_over_50_tau": bool(len(post) > 50 * tau),
+        "acceptance_per_rung": [round(float(a) / max(1, p), 4) for a, p in zip(st.accepted, st.proposed)],
+        "swap_rate": [round(float(a) / max(1, p), 4) for a, p in zip(st.swaps_accepted, st.swaps_proposed)],
+        "flow_acceptance": (round(st.flow_accepted / st.flow_proposed, 4) if st.flow_proposed else None),
+    }
+
+
+def ess_comparison(loglike: Callable, logprior: Callable, x0: np.ndarray, betas, seconds: float,
+                   seeds=(5, 55), a: float = 1.15, p_flow: float = 0.5, burn_frac: float = 0.3,
+                   max_train: int = 200000, flow_kwargs=None, fit_kwargs=None, log=None):
+    """Stretch-move PT against stretch + flow PT on the same target, from the
+    same start x0[T][W][D], each with the same wall budget 'seconds'.
+
+    Both arms drop their first burn_frac of the budget as burn-in; the flow
+    arm trains its proposal on the (thinned) T = 1 samples of that stretch-only
+    burn-in, and the training time is charged to it.  ESS (Sec. III.C) counts
+    only the post-burn-in T = 1 chain; ESS/s divides by the arm's whole wall
+    time.  Accuracy: per-parameter means of the two arms agree within 3
+    combined Monte Carlo standard errors, and standard deviations within 5 %.
+    """
+    say = log or (lambda *_: None)
+    dim = x0.shape[-1]
+    nw = x0.shape[1]
+    out = {}
+    # arm 1: stretch only
+    smp = PTSampler(loglike, logprior, betas, nw, dim, a=a, seed=seeds[0])
+    t0 = time.perf_counter()
+    smp.initialize(x0)
+    chain: list = []
+    _run_for(smp, burn_frac * seconds, chain, t0, say)
+    burn = len(chain)
+    _run_for(smp, seconds, chain, t0, say)
+    ch_plain = np.array(chain)
+    out["stretch"] = _arm_report(smp, ch_plain, time.perf_counter() - t0, burn)
+    say("stretch", out["stretch"])
+    # arm 2: stretch burn-in, flow training, then stretch + flow
+    prop = FlowProposal(dim, seed=seeds[1], **(flow_kwargs or {}))
+    smp2 = PTSampler(loglike, logprior, betas, nw, dim, a=a, seed=seeds[1], proposal=prop, p_flow=0.0)
+    t0 = time.perf_counter()
+    smp2.initialize(x0)
+    chain = []
+    _run_for(smp2, burn_frac * seconds, chain, t0, say)
+    burn2 = len(chain)
+    train = np.array(chain).reshape(-1, dim)
+    if len(train) > max_train:
+        train = train[np.linspace(0, len(train) - 1, max_train).astype(int)]
+    prop.fit(train, **(fit_kwargs or {}))
+    say("flow trained", {"samples": int(len(train)), "train_s": round(prop.train_seconds, 2),
+                         "final_loss": round(float(prop.losses[-1]), 4) if prop.losses else None})
+    smp2.p_flow = p_flow
+    _run_for(smp2, seconds, chain, t0, say)
+    ch_flow = np.array(chain)
+    out["stretch_flow"] = _arm_report(smp2, ch_flow, time.perf_counter() - t0, burn2)
+    out["stretch_flow"]["train_s"] = round(prop.train_seconds, 2)
+    out["stretch_flow"]["train_samples"] = int(len(train))
+    say("stretch+flow", out["stretch_flow"])
+    # equal posterior accuracy between the arms
+    a1, a2 = ch_plain[burn:].reshape(-1, dim), ch_flow[burn2:].reshape(-1, dim)
+    e1, e2 = max(out["stretch"]["ess"], 1.0), max(out["stretch_flow"]["ess"], 1.0)
+    se = np.sqrt(a1.var(0) / e1 + a2.var(0) / e2)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        zmax = float(np.nanmax(np.abs(a1.mean(0) - a2.mean(0)) / se))
+        sd_rel = float(np.nanmax(np.abs(a2.std(0) / a1.std(0) - 1)))
+    out["accuracy"] = {"max_mean_diff_in_se": round(zmax, 3), "max_sd_rel_diff": round(sd_rel, 4),
+                       "equal": bool(zmax < 3 and sd_rel < 0.05)}
+    out["ess_per_s_gain"] = round(out["stretch_flow"]["ess_per_s"] / max(out["stretch"]["ess_per_s"], 1e-12), 3)
+    prop.flow.close()
+    return out

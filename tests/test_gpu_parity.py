@@ -121,6 +121,26 @@ def test_determinism_and_batch_composition(small):
     torch.cuda.synchronize()
 
 
+def test_schedules_give_identical_bits(small):
+    """Every launch shape of the dense kernel (blocks per CU, one workgroup
+    per walker) and the autotuner's choice give bitwise the same ln L."""
+    import torch
+    w, psd, d, L = small
+    print("case: dense schedules / autotune", flush=True)
+    ref = L.loglike(w.walkers).cpu().numpy()
+    assert L.get_schedule() == (8, False)
+    for bpc, one in ((1, False), (3, False), (16, False), (8, True)):
+        L.set_schedule(bpc, one)
+        assert L.get_schedule() == (bpc, one)
+        assert np.array_equal(L.loglike(w.walkers).cpu().numpy(), ref)
+    best, ms = L.autotune(w.walkers, reps=3)
+    assert best in (2, 4, 6, 8, 12, 16) and ms > 0
+    assert L.get_schedule() == (best, False)
+    assert np.array_equal(L.loglike(w.walkers).cpu().numpy(), ref)
+    L.set_schedule(8, False)
+    torch.cuda.synchronize()
+
+
 def test_noiseless_injection_from_gpu_template_is_zero(small):
     import torch
     from paper_2005_01827_amd import mbh
@@ -210,3 +230,63 @@ def test_config2_1024_walkers_sampled(oracle):
 def test_config3_uneven_sampled(oracle):
     print("case: T_obs=2^25 grid, 2048 uneven walkers, 16 checked", flush=True)
     _full_case(oracle, inputs.config3(2048), 16, 2002, 2048)
+
+
+# ---------------------------------------------------------------------------
+# FP32 dense stage (compensated FP32 sums, FP64 phase and <d|d>).
+# Any FP32 rounding of the per-bin template with relative rms eps shifts
+# ln L by about Re<d-h, dh>, rms ~ eps sqrt(2) SNR in noise; with eps a few
+# 1e-7 the bound used here is 1e-6 SNR + 1e-6 |lnL| (the FP64 <d|d> term is
+# exact to ~1e-16 |lnL|; the compensated sums add no error at this level).
+# ---------------------------------------------------------------------------
+def _fp32_bound(ref):
+    snr = np.sqrt(np.maximum(ref[:, 4:7].sum(1), 0.0))
+    return 1e-6 * snr + 1e-6 * np.abs(ref[:, 0]) * 1e-6 + 1e-6
+
+
+def test_fp32c_small_grid(oracle):
+    import torch
+    from paper_2005_01827_amd import mbh
+    print("case: FP32C dense stage, small grid, 8 walkers", flush=True)
+    w = inputs.small_config(8, seed=7)
+    g = w.grid
+    psd = inputs.psd_aet(g.freqs)
+    d = oracle.template(w.injection, g, w.modes, w.ns, w.t0) + inputs.noise(g, psd, 77)
+    L = mbh.Likelihood(g, d, psd, w.modes, w.ns, w.t0, precision=mbh.MBH_FP32C, max_batch=16)
+    try:
+        out = L.stages(w.walkers).cpu().numpy()
+        lnl = L.loglike(w.walkers).cpu().numpy()
+        torch.cuda.synchronize()
+    finally:
+        L.close()
+    ref = oracle.loglike(w.walkers, g, d, psd, w.modes, w.ns, w.t0)
+    err = np.abs(out[:, 0] - ref[:, 0])
+    bound = _fp32_bound(ref)
+    print(f"[fp32c-small] |dlnL| = {err}  bound = {bound}", flush=True)
+    assert np.array_equal(lnl, out[:, 0])
+    assert np.all(err <= bound)
+    hh = ref[:, 4:7].sum(1)
+    assert np.all(np.abs(out[:, 4:7].sum(1) - hh) <= 1e-5 * hh)
+
+
+@pytest.mark.slow
+def test_fp32c_config2_sampled(oracle):
+    import torch
+    from paper_2005_01827_amd import mbh
+    print("case: FP32C, T_obs=2^25 grid, 1024 walkers, 12 checked", flush=True)
+    w = inputs.config2(1024)
+    g = w.grid
+    psd = inputs.psd_aet(g.freqs)
+    d = oracle.template(w.injection, g, w.modes, w.ns, w.t0) + inputs.noise(g, psd, 2002)
+    L = mbh.Likelihood(g, d, psd, w.modes, w.ns, w.t0, precision=mbh.MBH_FP32C, max_batch=1024)
+    try:
+        got = L.loglike(w.walkers).cpu().numpy()
+        torch.cuda.synchronize()
+    finally:
+        L.close()
+    idx = np.linspace(0, 1023, 12).astype(int)
+    ref = oracle.loglike(w.walkers[idx], g, d, psd, w.modes, w.ns, w.t0, nthreads=min(16, os.cpu_count()))
+    err = np.abs(got[idx] - ref[:, 0])
+    bound = _fp32_bound(ref)
+    print(f"[fp32c-cfg2] max |dlnL| = {err.max():.3e}  SNR ~ {np.sqrt(ref[:, 4:7].sum(1)).mean():.0f}", flush=True)
+    assert np.all(err <= bound)
