@@ -6,11 +6,13 @@
 // over each walker's union band, plus the data-only sum outside it from
 // per-channel prefix sums, so that ln L = -(R + DD_out)/2.
 //
-// Work decomposition: a walker's union band is cut into tiles of kTileBins
-// bins; work items (walker, tile) are numbered walker-major and processed by
-// a grid-stride loop.  Each item writes its 9 partial sums to its own slot,
-// and one wavefront per walker adds its slots in a fixed order, so results do
-// not depend on scheduling (no floating-point atomics).
+// Work decomposition: the dense grid is cut into tiles of kTileBins bins;
+// work items (walker, tile) cover each walker's union band and are listed
+// tile-major (all walkers of tile 0, then tile 1, ...) for a grid-stride
+// loop, so that workgroups running together share a few data tiles in L2.
+// Each item writes its 9 partial sums to a walker-major slot, and one
+// wavefront per walker adds its slots in a fixed order, so results do not
+// depend on the order or the launch shape (no floating-point atomics).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -173,14 +175,86 @@ __global__ void k_scan_walkers(int B, const WalkerBand *__restrict__ wb, int *__
     if (threadIdx.x == 0) wbase[B] = carry;
 }
 
-__global__ void k_fill_items(int B, const WalkerBand *__restrict__ wb, const int *__restrict__ wbase,
-                             int *__restrict__ item_w, int max_items)
+// Work items in tile-major order: all walkers whose band covers tile 0, in
+// walker order, then tile 1, and so on.  Workgroups that run at the same time
+// then share the same few data tiles, which stay in L2 instead of every
+// walker streaming its whole band from memory.  Partial-sum slots stay
+// walker-major (slot = wbase[w] + tile - tile_lo), so the reduction, and with
+// it every bit of ln L, does not depend on the order.
+__device__ __forceinline__ bool covers(const WalkerBand &b, int t)
 {
-    const int w = blockIdx.x;
-    if (w >= B) return;
-    const int base = wbase[w], nt = wb[w].ntiles;
-    for (int j = threadIdx.x; j < nt; j += blockDim.x)
-        if (base + j < max_items) item_w[base + j] = w;
+    return t >= b.tile_lo && t < b.tile_lo + b.ntiles;
+}
+
+// count of walkers per tile; one workgroup per tile
+__global__ __launch_bounds__(256) void k_tile_count(int B, const WalkerBand *__restrict__ wb,
+                                                    int *__restrict__ tile_off)
+{
+    __shared__ int red[256];
+    const int t = blockIdx.x;
+    int c = 0;
+    for (int w = threadIdx.x; w < B; w += 256) c += covers(wb[w], t) ? 1 : 0;
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tile_off[t] = red[0];
+}
+
+// exclusive scan of the per-tile counts in place (single workgroup of 1024)
+__global__ __launch_bounds__(1024) void k_tile_scan(int ntiles, int *__restrict__ tile_off)
+{
+    __shared__ int sh[1024];
+    int carry = 0;
+    for (int b0 = 0; b0 < ntiles; b0 += 1024) {
+        const int i = b0 + threadIdx.x;
+        const int v = (i < ntiles) ? tile_off[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int a = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += a;
+            __syncthreads();
+        }
+        if (i < ntiles) tile_off[i] = carry + sh[threadIdx.x] - v;
+        const int tot = sh[1023];
+        __syncthreads();
+        carry += tot;
+    }
+    if (threadIdx.x == 0) tile_off[ntiles] = carry;
+}
+
+// the walkers of each tile, compacted in walker order; one workgroup per tile
+__global__ __launch_bounds__(256) void k_tile_fill(int B, const WalkerBand *__restrict__ wb,
+                                                   const int *__restrict__ tile_off, int *__restrict__ item_w,
+                                                   int *__restrict__ item_t, int max_items)
+{
+    __shared__ int sh[256];
+    const int t = blockIdx.x;
+    int run = tile_off[t];
+    for (int w0 = 0; w0 < B; w0 += 256) {
+        const int w = w0 + threadIdx.x;
+        const int f = (w < B && covers(wb[w], t)) ? 1 : 0;
+        sh[threadIdx.x] = f;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const int a = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += a;
+            __syncthreads();
+        }
+        const int pos = run + sh[threadIdx.x] - f;
+        if (f && pos < max_items) {
+            item_w[pos] = w;
+            item_t[pos] = t;
+        }
+        const int tot = sh[255];
+        __syncthreads();
+        run += tot;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -195,6 +269,7 @@ struct DenseArgs {
     const WalkerBand *wband;
     const int *wbase;
     const int *item_w;
+    const int *item_t;
     const double *kf;
     const int *kbin;
     const double *coef;
@@ -265,21 +340,17 @@ __device__ __forceinline__ void cis(const CisConst &K, double phi, double &sn, d
     cs = ((iq + 1) & 2) ? -b : b;
 }
 
-// Cubic c0 + c1 x + c2 x^2 + c3 x^3.  From a wave-uniform table (scalar
-// registers) the first step is a multiply, because a VALU instruction reads
-// at most one scalar operand, and x enters as |x|: x = f - f_i >= 0 inside
-// interval i (the integer bin bounds guarantee k df >= f_i), and the |.|
-// source modifier makes the compiler emit the three-operand FMA that reads
-// the scalar coefficient in place instead of copying it into vector
-// registers for the two-operand accumulate form.  From per-lane registers
-// it is plain Horner.
+// Cubic c0 + c1 x + c2 x^2 + c3 x^3 by Horner's rule starting with an FMA,
+// both from a wave-uniform table (scalar registers) and from per-lane
+// registers.  With scalar coefficients the first FMA needs c3 copied to a
+// vector register (a VALU instruction reads at most one scalar operand).
+// Starting instead with the product c3 * x read from a scalar register was
+// measured to drop the c3 x^3 term on gfx950 when x had just been computed
+// (reproduced by a one-wavefront test kernel), so that form is not used; the
+// parity tests against the oracle guard this choice.
 __device__ __forceinline__ double cubic_s(cdouble *c, double x)
 {
-    const double ax = fabs(x);
-    double p = c[3] * ax;
-    p = fma(p, ax, c[2]);
-    p = fma(p, ax, c[1]);
-    return fma(p, ax, c[0]);
+    return fma(fma(fma(c[3], x, c[2]), x, c[1]), x, c[0]);
 }
 __device__ __forceinline__ double cubic_v(const double *c, double x)
 {
@@ -368,11 +439,7 @@ __device__ __forceinline__ void cis32(const CisConst &K, const CisConst32 &Kf, d
 
 __device__ __forceinline__ float cubic32_s(cfloat *c, float x)
 {
-    const float ax = fabsf(x);
-    float p = c[3] * ax;
-    p = fmaf(p, ax, c[2]);
-    p = fmaf(p, ax, c[1]);
-    return fmaf(p, ax, c[0]);
+    return fmaf(fmaf(fmaf(c[3], x, c[2]), x, c[1]), x, c[0]);
 }
 __device__ __forceinline__ float cubic32_v(const float *c, float x)
 {
@@ -449,9 +516,10 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs a)
         step = 1;
     }
     for (; item < end; item += step) {
-        const int wk = uni_i(a.item_w[item]);
+        const int wk = a.one_per_walker ? (int)blockIdx.x : uni_i(a.item_w[item]);
         const WalkerBand wb = a.wband[wk];
-        const int tile = wb.tile_lo + (item - a.wbase[wk]);
+        const int tile = a.one_per_walker ? wb.tile_lo + (item - a.wbase[wk]) : uni_i(a.item_t[item]);
+        const int slot = a.wbase[wk] + (tile - wb.tile_lo);
         const int kw = uni_i(a.k0 + tile * kTileBins + wave * (64 * kDenseJ));
         const int kwl = kw + 64 * kDenseJ - 1;
 
@@ -595,7 +663,7 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs a)
             double s = 0.0;
 #pragma unroll
             for (int wv = 0; wv < kDenseThreads / 64; ++wv) s += red[wv][threadIdx.x];
-            a.partial[(size_t)item * kPartials + threadIdx.x] = s;
+            a.partial[(size_t)slot * kPartials + threadIdx.x] = s;
         }
         __syncthreads();
     }
@@ -672,6 +740,7 @@ DenseArgs make_args(int B, const Modes &md, const GridDesc &g, const Work &wk, c
     a.wband = wk.wband;
     a.wbase = wk.wbase;
     a.item_w = wk.item_w;
+    a.item_t = wk.item_t;
     a.kf = wk.kf;
     a.kbin = wk.kbin;
     a.coef = wk.coef;
@@ -757,11 +826,19 @@ hipError_t launch_walker_bands(int B, const Modes &md, const GridDesc &g, const 
     return hipGetLastError();
 }
 
+void launch_items(int B, const GridDesc &g, const Work &wk, int max_items, hipStream_t st)
+{
+    const int ntiles = (g.n + kTileBins - 1) / kTileBins;
+    k_tile_count<<<ntiles, 256, 0, st>>>(B, wk.wband, wk.tile_off);
+    k_tile_scan<<<1, 1024, 0, st>>>(ntiles, wk.tile_off);
+    k_tile_fill<<<ntiles, 256, 0, st>>>(B, wk.wband, wk.tile_off, wk.item_w, wk.item_t, max_items);
+}
+
 hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &wk, const Data &dt, int max_items,
                         const Schedule &sch, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (B <= 0) return hipSuccess;
-    k_fill_items<<<B, 256, 0, st>>>(B, wk.wband, wk.wbase, wk.item_w, max_items);
+    launch_items(B, g, wk, max_items, st);
     DenseArgs a = make_args(B, md, g, wk, dt, max_items);
     a.one_per_walker = sch.one_per_walker;
     const int grid = dense_grid(B, sch);
@@ -797,7 +874,7 @@ hipError_t launch_template(const Modes &md, const GridDesc &g, const Work &wk, d
     const long long nh = 3LL * g.n;
     k_zero2<<<(unsigned)((nh + 255) / 256), 256, 0, st>>>(h, nh);
     const int max_items = (g.n + kTileBins - 1) / kTileBins + 1;
-    k_fill_items<<<1, 256, 0, st>>>(1, wk.wband, wk.wbase, wk.item_w, max_items);
+    launch_items(1, g, wk, max_items, st);
     DenseArgs a = make_args(1, md, g, wk, none, max_items);
     a.h = h;
     k_dense<true, false><<<dense_grid(1, Schedule()), kDenseThreads, 0, st>>>(a);

@@ -193,8 +193,11 @@ class PTSampler:
                 use_flow = (self.rng.random((self.nt, half)) < self.p_flow) & (self.betas[:, None] > 0.0)
                 nf = int(use_flow.sum())
                 if nf:
-                    xf, lq_new = self.proposal.sample(nf, self.rng)
-                    lq_old = self.proposal.logq(xa[use_flow])
+                    if hasattr(self.proposal, "propose"):
+                        xf, lq_new, lq_old = self.proposal.propose(xa[use_flow], self.rng)
+                    else:
+                        xf, lq_new = self.proposal.sample(nf, self.rng)
+                        lq_old = self.proposal.logq(xa[use_flow])
                     prop[use_flow] = xf
                     log_corr[use_flow] = lq_old - lq_new      # q(x)/q(x') for an independence proposal
             lp, ll = self._eval(prop.reshape(-1, self.dim))
@@ -307,8 +310,11 @@ class FlowProposal:
         self.losses = []
         self.train_seconds = 0.0
 
-    def fit(self, x: np.ndarray, steps: int = 400, lr: float = 2e-3, batch: int = 4096, seed: int = 0):
-        """Adam on minibatches of the samples x [N][dim]; returns the losses."""
+    def fit(self, x: np.ndarray, steps: int = 400, lr: float = 2e-3, batch: int = 4096, seed: int = 0,
+            lr_final: float = None):
+        """Adam on minibatches of the samples x [N][dim], the learning rate
+        decaying geometrically from lr to lr_final (default lr / 20); returns
+        the losses."""
         import torch
         t0 = time.perf_counter()
         x = np.asarray(x, dtype=np.float64).reshape(-1, self.dim)
@@ -317,14 +323,32 @@ class FlowProposal:
         u = torch.as_tensor(((x - self.mu) / self.sd).astype(np.float32), device="cuda")
         rng = np.random.default_rng(seed)
         batch = min(batch, len(x), self.flow.max_batch)
-        for _ in range(steps):
+        lr_final = lr / 20 if lr_final is None else lr_final
+        decay = (lr_final / lr) ** (1.0 / max(steps - 1, 1))
+        shift = float(np.sum(np.log(self.sd)))
+        for i in range(steps):
             idx = torch.as_tensor(rng.integers(0, len(x), batch), device="cuda")
             loss, _ = self.flow.loss_grad(u.index_select(0, idx), want_grad=False)
-            self.flow.adam(lr)
-            self.losses.append(loss + float(np.sum(np.log(self.sd))))
+            self.flow.adam(lr * decay ** i)
+            self.losses.append(loss + shift)
         torch.cuda.synchronize()
         self.train_seconds += time.perf_counter() - t0
         return self.losses
+
+    def propose(self, x_old: np.ndarray, rng: np.random.Generator):
+        """n = len(x_old) draws x' ~ q with log q(x') and log q(x_old), in one
+        host-to-device copy, an inverse and a forward pass, and one copy back."""
+        import torch
+        n = len(x_old)
+        z = rng.standard_normal((n, self.dim)).astype(np.float32)
+        u_old = ((np.asarray(x_old) - self.mu) / self.sd).astype(np.float32)
+        dev = torch.as_tensor(np.concatenate([z, u_old]), device="cuda")
+        u_new, _ = self.flow.inverse(dev[:n])
+        _, lq = self.flow.forward(torch.cat([u_new, dev[n:]]))
+        out = torch.cat([u_new.reshape(-1), lq]).cpu().numpy().astype(np.float64)
+        u = out[:n * self.dim].reshape(n, self.dim)
+        lq = out[n * self.dim:] - float(np.sum(np.log(self.sd)))
+        return self.mu + self.sd * u, lq[:n], lq[n:]
 
     def logq(self, x: np.ndarray) -> np.ndarray:
         u = (np.atleast_2d(x) - self.mu) / self.sd
