@@ -32,7 +32,7 @@ FP64_PEAK_TFLOPS = 78.6            # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 
 FLOPS_PER_MODE_BIN = 111           # 8 cubics 48, e^{i phi} 37, A e^{i phi} 2, 3 complex MACs 24
 FLOPS_PER_WALKER_BIN = 51          # per channel: d-h 2, |r|^2 w 5, Re(d h*) w 5, |h|^2 w 5
 BYTES_PER_WALKER_BIN = 72          # d (3 x complex128) + w (3 x float64), streamed per walker
-KERNEL_REV = "dense-v7"            # traffic counters are only reused for this kernel revision
+KERNEL_REV = "dense-v9"            # traffic counters are only reused for this kernel revision
 
 
 def parse():
@@ -49,6 +49,8 @@ def parse():
                     help="instead of the throughput line, run the learned-proposal comparison: PT (8 rungs x "
                          "--sampler-walkers walkers, a = 1.15) on the workload's data, stretch only against "
                          "stretch + flow, SECONDS of wall time per arm; prints one JSON line")
+    ap.add_argument("--sampler-burn", type=float, default=60.0, metavar="SECONDS",
+                    help="shared stretch-only burn-in before the two arms of --sampler")
     ap.add_argument("--sampler-walkers", type=int, default=512)
     ap.add_argument("--sampler-rungs", type=int, default=8)
     ap.add_argument("--schedule-study", action="store_true",
@@ -110,18 +112,19 @@ def sampler_comparison(args):
     h = L0.template(w.injection).cpu().numpy()
     L0.close()
     data = h + inputs.noise(g, psd, w.noise_seed)
-    L = mbh.Likelihood(g, data, psd, w.modes, w.ns, w.t0, max_batch=nt * nw // 2)
+    L = mbh.Likelihood(g, data, psd, w.modes, w.ns, w.t0, max_batch=nt * nw)
     x0 = inputs.to_sampling(w.walkers).reshape(nt, nw, -1)
     log = lambda name, rep: print(f"# {name}: {json.dumps(rep)}", file=sys.stderr, flush=True)
-    rep = S.ess_comparison(S.gpu_loglike(L), S.box_logprior(), x0, S.ladder(nt), args.sampler, seeds=(5, 55),
-                           a=1.15, log=log, fit_kwargs={"steps": 600, "lr": 1e-3, "batch": 4096})
+    rep = S.ess_comparison(S.gpu_loglike(L), S.box_logprior(), x0, S.ladder(nt), args.sampler,
+                           args.sampler_burn, seeds=(5, 55), a=1.15, log=log,
+                           fit_kwargs={"steps": 800, "lr": 2e-3, "batch": 4096})
     torch.cuda.synchronize()
     result = {"metric": "ESS/s at T = 1, stretch + learned proposal vs stretch only", "unit": "ESS/s",
               "value": rep["stretch_flow"]["ess_per_s"], "baseline_value": rep["stretch"]["ess_per_s"],
               "gain": rep["ess_per_s_gain"], "higher_is_better": True, "n_gpus": 1, "dtype": "f64",
               "data": "synthetic (seeded injection + Gaussian noise, analytic PSD)",
               "config": {"workload": w.name, "rungs": nt, "walkers_per_rung": nw, "stretch_a": 1.15,
-                         "seconds_per_arm": args.sampler, "seeds": [5, 55]},
+                         "burn_in_seconds": args.sampler_burn, "seconds_per_arm": args.sampler, "seeds": [5, 55]},
               "report": rep}
     print(json.dumps(result), flush=True)
     L.close()

@@ -311,9 +311,22 @@ struct CisConst {
     double k[kCisN];
 };
 
+// A zero the compiler cannot prove wave-uniform: indexing with it turns a
+// table read into per-lane vector loads, so the values live in VGPRs.
+__device__ __forceinline__ int lane_zero()
+{
+    int z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    return z;
+}
+
+// The sin/cos constants are held in VGPRs (34 of them): in scalar registers
+// they pushed the per-mode interval state and the coefficient blocks into
+// SGPR spills, whose reloads cost more VALU issue than the VGPRs cost
+// occupancy (measured: 20.4 ms against 23.3 ms for a 1024-walker sweep).
 __device__ __forceinline__ void load_cis(CisConst &K, const double *tab)
 {
-    cdouble *t = (cdouble *)tab;
+    const double *t = tab + lane_zero();
 #pragma unroll
     for (int i = 0; i < kCisN; ++i) K.k[i] = t[i];
 }
@@ -340,17 +353,22 @@ __device__ __forceinline__ void cis(const CisConst &K, double phi, double &sn, d
     cs = ((iq + 1) & 2) ? -b : b;
 }
 
-// Cubic c0 + c1 x + c2 x^2 + c3 x^3 by Horner's rule starting with an FMA,
-// both from a wave-uniform table (scalar registers) and from per-lane
-// registers.  With scalar coefficients the first FMA needs c3 copied to a
-// vector register (a VALU instruction reads at most one scalar operand).
-// Starting instead with the product c3 * x read from a scalar register was
-// measured to drop the c3 x^3 term on gfx950 when x had just been computed
-// (reproduced by a one-wavefront test kernel), so that form is not used; the
-// parity tests against the oracle guard this choice.
+// Cubic c0 + c1 x + c2 x^2 + c3 x^3 from a wave-uniform table (scalar
+// registers), by Horner's rule with alternating signs:
+//   u = -(c3 x + c2),  v = u x - c1,  result = -v x + c0.
+// Every FMA carries a negation modifier, which only the three-operand
+// encoding can express, so each reads its scalar coefficient in place; the
+// plain form is compiled to the two-operand accumulate FMA with every
+// coefficient first copied to vector registers (6 moves per cubic).  Only c2
+// (the first FMA has two scalar operands) is copied.  Starting instead with
+// the product c3 * x from a scalar register was measured to drop the c3 x^3
+// term on gfx950 when x had just been computed (reproduced by a one-wavefront
+// test kernel), so that form is not used; the parity tests guard this.
 __device__ __forceinline__ double cubic_s(cdouble *c, double x)
 {
-    return fma(fma(fma(c[3], x, c[2]), x, c[1]), x, c[0]);
+    const double u = fma(-c[3], x, -c[2]);
+    const double v = fma(u, x, -c[1]);
+    return fma(-v, x, c[0]);
 }
 __device__ __forceinline__ double cubic_v(const double *c, double x)
 {

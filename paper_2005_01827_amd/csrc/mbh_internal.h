@@ -77,7 +77,9 @@ struct Work {
     double *coef;           // [B][nm][ns-1][8][4] spline coefficients
     double *spline_scratch; // [B][nm][8][2 ns]
     int *kbin;              // [B][nm][ns] first dense bin k with k df >= knot
-    int *item_w;            // [max items] walker of each work item
+    int *item_w;            // [max items] walker of each work item (tile-major order)
+    int *item_t;            // [max items] tile of each work item
+    int *tile_off;          // [tiles + 1] first item of each tile
     int *wbase;             // [B+1]  exclusive scan of ntiles; wbase[B] = total
     double *partial;        // [max items][9]
     double *out7;           // [B][7] default output

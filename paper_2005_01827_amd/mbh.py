@@ -358,23 +358,30 @@ class Flow:
         self._check(self.lib.mbh_flow_set_params(self.flow, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
                     "mbh_flow_set_params")
 
-    def forward(self, u, stream=None):
-        """(z, log q(u)) as CUDA tensors."""
+    def _outs(self, n, out):
+        if out is not None:
+            a, lq = out
+            if a.shape != (n, self.dim) or lq.shape != (n,) or not (a.is_contiguous() and lq.is_contiguous()):
+                raise ValueError("out must be contiguous ([n][dim], [n]) float32 CUDA tensors")
+            return a, lq
+        t = self._torch
+        return t.empty((n, self.dim), dtype=t.float32, device="cuda"), t.empty(n, dtype=t.float32, device="cuda")
+
+    def forward(self, u, stream=None, out=None):
+        """(z, log q(u)) as CUDA tensors (written into out=(z, lq) if given)."""
         u = self._rows(u)
         n = u.shape[0]
-        z = self._torch.empty_like(u)
-        lq = self._torch.empty(n, dtype=self._torch.float32, device="cuda")
+        z, lq = self._outs(n, out)
         self._check(self.lib.mbh_flow_forward(self.flow, ctypes.c_void_p(u.data_ptr()), n,
                                               ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(lq.data_ptr()),
                                               self._stream(stream)), "mbh_flow_forward")
         return z, lq
 
-    def inverse(self, z, stream=None):
-        """(u = f^-1(z), log q(u)) as CUDA tensors."""
+    def inverse(self, z, stream=None, out=None):
+        """(u = f^-1(z), log q(u)) as CUDA tensors (written into out=(u, lq) if given)."""
         z = self._rows(z)
         n = z.shape[0]
-        u = self._torch.empty_like(z)
-        lq = self._torch.empty(n, dtype=self._torch.float32, device="cuda")
+        u, lq = self._outs(n, out)
         self._check(self.lib.mbh_flow_inverse(self.flow, ctypes.c_void_p(z.data_ptr()), n,
                                               ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(lq.data_ptr()),
                                               self._stream(stream)), "mbh_flow_inverse")

@@ -130,11 +130,13 @@ class PTSampler:
       density); called once per half-step with all rungs batched.
     logprior: callable x[N][D] -> ln prior (-inf outside the support).
     proposal: optional independence proposal with .sample(n, rng) -> (x, logq)
-      and .logq(x) -> logq; used with probability p_flow at beta > 0 rungs.
+      and .logq(x) -> logq (or .propose(x_old, rng) -> (x, logq, logq_old));
+      used with probability p_flow at rungs with beta >= flow_beta_min
+      (default: the beta = 1 rungs whose posterior it was trained on).
     """
 
     def __init__(self, loglike: Callable, logprior: Callable, betas, n_walkers: int, dim: int,
-                 a: float = 1.15, seed: int = 0, proposal=None, p_flow: float = 0.0):
+                 a: float = 1.15, seed: int = 0, proposal=None, p_flow: float = 0.0, flow_beta_min: float = 1.0):
         if n_walkers % 2 or n_walkers < 4:
             raise ValueError("n_walkers must be even and >= 4")
         self.loglike = loglike
@@ -147,6 +149,7 @@ class PTSampler:
         self.rng = np.random.Generator(np.random.PCG64(seed))
         self.proposal = proposal
         self.p_flow = p_flow
+        self.flow_beta_min = flow_beta_min   # the proposal models the beta = 1 posterior
         self.state: Optional[PTState] = None
         self.n_like_calls = 0
         self.like_seconds = 0.0
@@ -190,7 +193,8 @@ class PTSampler:
             log_corr = (self.dim - 1) * np.log(Y)                # stretch-move Jacobian term
             use_flow = np.zeros((self.nt, half), bool)
             if self.proposal is not None and self.p_flow > 0.0:
-                use_flow = (self.rng.random((self.nt, half)) < self.p_flow) & (self.betas[:, None] > 0.0)
+                use_flow = ((self.rng.random((self.nt, half)) < self.p_flow)
+                            & (self.betas[:, None] >= self.flow_beta_min) & (self.betas[:, None] > 0.0))
                 nf = int(use_flow.sum())
                 if nf:
                     if hasattr(self.proposal, "propose"):
@@ -291,75 +295,159 @@ class PTSampler:
 
 
 class FlowProposal:
-    """Independence proposal from the learned affine-coupling flow (mbh.Flow).
+    """Independence proposal: a defensive mixture of the learned affine-coupling
+    flow (mbh.Flow) and a broad Gaussian,
+        q(x) = (1 - eps) q_flow(x) + eps N(x; m, (infl^2) C),
+    with m and C the mean and covariance of the training samples.  The
+    Gaussian component bounds pi/q where the flow under-covers the target
+    (tails the training chain has not explored), so no walker sticks.
 
-    The flow models standardized coordinates u = (x - mu) / sd, with mu and sd
-    taken from the training samples, so log q_x(x) = log q_u(u) - sum log sd.
-    Draws are u = f^{-1}(z) with z ~ N(0, I) from the sampler's generator.
-    Both densities in the acceptance ratio are evaluated by the same forward
-    pass, so q is one deterministic function of x.
+    The flow models standardized coordinates u = (x - mu) / sd, so
+    log q_flow(x) = log q_u(u) - sum log sd; it is evaluated as the forward
+    pass of float32(u), one deterministic function of x.
     """
 
     def __init__(self, dim: int, n_layers: int = 8, hidden: int = 128, max_batch: int = 65536, seed: int = 0,
-                 flow=None):
+                 flow=None, defensive: float = 0.1, inflate: float = 1.5):
         from . import mbh
+        if not 0.0 <= defensive < 1.0:
+            raise ValueError("defensive weight must be in [0, 1)")
         self.dim = dim
         self.flow = flow if flow is not None else mbh.Flow(dim, n_layers, hidden, max_batch, seed=seed)
+        self.eps = defensive
+        self.inflate = inflate
         self.mu = np.zeros(dim)
         self.sd = np.ones(dim)
+        self.m = np.zeros(dim)
+        self.chol = np.eye(dim)
+        self.cinv = np.eye(dim)
+        self.gnorm = -0.5 * dim * math.log(2 * math.pi)
         self.losses = []
+        self.val_losses = []
         self.train_seconds = 0.0
 
-    def fit(self, x: np.ndarray, steps: int = 400, lr: float = 2e-3, batch: int = 4096, seed: int = 0,
-            lr_final: float = None):
-        """Adam on minibatches of the samples x [N][dim], the learning rate
-        decaying geometrically from lr to lr_final (default lr / 20); returns
-        the losses."""
+    def fit(self, x: np.ndarray, steps: int = 600, lr: float = 2e-3, batch: int = 4096, seed: int = 0,
+            lr_final: float = None, val_frac: float = 0.2, val_every: int = 25):
+        """Adam on minibatches of the samples x [N][dim] (in chain order), the
+        learning rate decaying geometrically from lr to lr_final (default
+        lr / 20).  The last val_frac of the samples is held out; the
+        parameters with the lowest held-out loss are kept."""
         import torch
         t0 = time.perf_counter()
         x = np.asarray(x, dtype=np.float64).reshape(-1, self.dim)
         self.mu = x.mean(axis=0)
         self.sd = x.std(axis=0) + 1e-12
-        u = torch.as_tensor(((x - self.mu) / self.sd).astype(np.float32), device="cuda")
+        cov = np.cov(x.T) * self.inflate ** 2 + np.diag((1e-12 * self.sd) ** 2)
+        self.m = self.mu.copy()
+        self.chol = np.linalg.cholesky(cov)
+        self.cinv = np.linalg.inv(cov)
+        self.gnorm = -0.5 * (self.dim * math.log(2 * math.pi) + np.linalg.slogdet(cov)[1])
+        u_all = torch.as_tensor(((x - self.mu) / self.sd).astype(np.float32), device="cuda")
+        nv = int(len(x) * val_frac) if len(x) > 10 else 0
+        u, uv = u_all[: len(x) - nv], u_all[len(x) - nv:]
         rng = np.random.default_rng(seed)
-        batch = min(batch, len(x), self.flow.max_batch)
+        batch = min(batch, len(u), self.flow.max_batch)
         lr_final = lr / 20 if lr_final is None else lr_final
         decay = (lr_final / lr) ** (1.0 / max(steps - 1, 1))
         shift = float(np.sum(np.log(self.sd)))
+        best, best_p = float("inf"), None
         for i in range(steps):
-            idx = torch.as_tensor(rng.integers(0, len(x), batch), device="cuda")
+            idx = torch.as_tensor(rng.integers(0, len(u), batch), device="cuda")
             loss, _ = self.flow.loss_grad(u.index_select(0, idx), want_grad=False)
             self.flow.adam(lr * decay ** i)
             self.losses.append(loss + shift)
+            if nv and (i % val_every == val_every - 1 or i == steps - 1):
+                vl = 0.0
+                for b0 in range(0, nv, self.flow.max_batch):
+                    _, lq = self.flow.forward(uv[b0:b0 + self.flow.max_batch])
+                    vl -= float(lq.double().sum())
+                vl = vl / nv + shift
+                self.val_losses.append(vl)
+                if vl < best:
+                    best, best_p = vl, self.flow.get_params()
+        if best_p is not None:
+            self.flow.set_params(best_p)
         torch.cuda.synchronize()
         self.train_seconds += time.perf_counter() - t0
         return self.losses
 
-    def propose(self, x_old: np.ndarray, rng: np.random.Generator):
-        """n = len(x_old) draws x' ~ q with log q(x') and log q(x_old), in one
-        host-to-device copy, an inverse and a forward pass, and one copy back."""
-        import torch
-        n = len(x_old)
-        z = rng.standard_normal((n, self.dim)).astype(np.float32)
-        u_old = ((np.asarray(x_old) - self.mu) / self.sd).astype(np.float32)
-        dev = torch.as_tensor(np.concatenate([z, u_old]), device="cuda")
-        u_new, _ = self.flow.inverse(dev[:n])
-        _, lq = self.flow.forward(torch.cat([u_new, dev[n:]]))
-        out = torch.cat([u_new.reshape(-1), lq]).cpu().numpy().astype(np.float64)
-        u = out[:n * self.dim].reshape(n, self.dim)
-        lq = out[n * self.dim:] - float(np.sum(np.log(self.sd)))
-        return self.mu + self.sd * u, lq[:n], lq[n:]
+    def _logq_gauss(self, x):
+        d = np.atleast_2d(x) - self.m
+        return self.gnorm - 0.5 * np.einsum("ni,ij,nj->n", d, self.cinv, d)
+
+    def _mix(self, lq_flow, x):
+        lq_flow = lq_flow - float(np.sum(np.log(self.sd)))
+        if self.eps == 0.0:
+            return lq_flow
+        return np.logaddexp(math.log1p(-self.eps) + lq_flow, math.log(self.eps) + self._logq_gauss(x))
 
     def logq(self, x: np.ndarray) -> np.ndarray:
-        u = (np.atleast_2d(x) - self.mu) / self.sd
-        _, lq = self.flow.forward(u.astype(np.float32))
-        return lq.cpu().numpy().astype(np.float64) - float(np.sum(np.log(self.sd)))
+        x = np.atleast_2d(x)
+        _, lq = self.flow.forward(((x - self.mu) / self.sd).astype(np.float32))
+        return self._mix(lq.cpu().numpy().astype(np.float64), x)
+
+    def _buffers(self, rows):
+        """Pinned host and device staging for up to 'rows' rows (grown on demand)."""
+        import torch
+        if getattr(self, "_cap", 0) < rows:
+            cap = max(rows, 256)
+            f32 = torch.float32
+            self._h_in = torch.empty((3 * cap, self.dim), dtype=f32, pin_memory=True)
+            self._h_out = torch.empty(cap * self.dim + 3 * cap, dtype=f32, pin_memory=True)
+            self._d_in = torch.empty((3 * cap, self.dim), dtype=f32, device="cuda")
+            self._d_u = torch.empty((3 * cap, self.dim), dtype=f32, device="cuda")
+            self._d_z = torch.empty((3 * cap, self.dim), dtype=f32, device="cuda")
+            self._d_lq = torch.empty(3 * cap, dtype=f32, device="cuda")
+            self._d_lqi = torch.empty(cap, dtype=f32, device="cuda")
+            self._cap = cap
+
+    def propose(self, x_old: np.ndarray, rng: np.random.Generator):
+        """len(x_old) draws x' ~ q with log q(x') and log q(x_old).
+
+        Per chunk of rows: one copy of [z; u_gauss; u_old] to the device, an
+        inverse pass for the flow draws, one forward pass over the flow draws,
+        the Gaussian draws and the old points, and one copy back."""
+        import torch
+        x_old = np.atleast_2d(x_old)
+        n_all = len(x_old)
+        gauss = rng.random(n_all) < self.eps
+        zn = rng.standard_normal((n_all, self.dim))
+        xg = self.m + zn @ self.chol.T
+        chunk = max(1, self.flow.max_batch // 3)
+        x_new = np.empty((n_all, self.dim))
+        lq_f_new = np.empty(n_all)
+        lq_f_old = np.empty(n_all)
+        for c0 in range(0, n_all, chunk):
+            c1 = min(n_all, c0 + chunk)
+            n = c1 - c0
+            self._buffers(n)
+            h = self._h_in.numpy()
+            h[:n] = zn[c0:c1]
+            h[n:2 * n] = (xg[c0:c1] - self.mu) / self.sd
+            h[2 * n:3 * n] = (x_old[c0:c1] - self.mu) / self.sd
+            d_in, d_u = self._d_in[:3 * n], self._d_u[:3 * n]
+            d_in.copy_(self._h_in[:3 * n], non_blocking=True)
+            self.flow.inverse(d_in[:n], out=(d_u[:n], self._d_lqi[:n]))
+            d_u[n:].copy_(d_in[n:])
+            self.flow.forward(d_u, out=(self._d_z[:3 * n], self._d_lq[:3 * n]))
+            ho = self._h_out
+            ho[:n * self.dim].view(n, self.dim).copy_(d_u[:n], non_blocking=True)
+            ho[n * self.dim:n * self.dim + 3 * n].copy_(self._d_lq[:3 * n], non_blocking=True)
+            torch.cuda.current_stream().synchronize()
+            o = ho.numpy()
+            u_flow = o[:n * self.dim].reshape(n, self.dim).astype(np.float64)
+            lq = o[n * self.dim:n * self.dim + 3 * n].astype(np.float64)
+            g = gauss[c0:c1]
+            u_g = h[n:2 * n].astype(np.float64)
+            x_new[c0:c1] = self.mu + self.sd * np.where(g[:, None], u_g, u_flow)
+            lq_f_new[c0:c1] = np.where(g, lq[n:2 * n], lq[:n])
+            lq_f_old[c0:c1] = lq[2 * n:]
+        return x_new, self._mix(lq_f_new, x_new), self._mix(lq_f_old, x_old)
 
     def sample(self, n: int, rng: np.random.Generator):
-        z = rng.standard_normal((n, self.dim)).astype(np.float32)
-        u, _ = self.flow.inverse(z)
-        x = self.mu + self.sd * u.cpu().numpy().astype(np.float64)
-        return x, self.logq(x)
+        """n draws x ~ q and log q(x)."""
+        x, lq, _ = self.propose(np.tile(self.mu, (n, 1)), rng)
+        return x, lq
 
 
 def box_logprior(lo=inputs.PRIOR_LO, hi=inputs.PRIOR_HI):
@@ -413,56 +501,63 @@ def _arm_report(smp: PTSampler, chain: np.ndarray, wall: float, burn: int):
 
 
 def ess_comparison(loglike: Callable, logprior: Callable, x0: np.ndarray, betas, seconds: float,
-                   seeds=(5, 55), a: float = 1.15, p_flow: float = 0.5, burn_frac: float = 0.3,
+                   burn_seconds: float, seeds=(5, 55), a: float = 1.15, p_flow: float = 0.8,
                    max_train: int = 200000, flow_kwargs=None, fit_kwargs=None, log=None):
-    """Stretch-move PT against stretch + flow PT on the same target, from the
-    same start x0[T][W][D], each with the same wall budget 'seconds'.
+    """Stretch-move PT against stretch + flow PT on the same target.
 
-    Both arms drop their first burn_frac of the budget as burn-in; the flow
-    arm trains its proposal on the (thinned) T = 1 samples of that stretch-only
-    burn-in, and the training time is charged to it.  ESS (Sec. III.C) counts
-    only the post-burn-in T = 1 chain; ESS/s divides by the arm's whole wall
-    time.  Accuracy: per-parameter means of the two arms agree within 3
-    combined Monte Carlo standard errors, and standard deviations within 5 %.
+    One stretch-only burn-in of burn_seconds from x0[T][W][D] is shared and
+    charged to neither arm.  From its final state the plain arm keeps
+    running, and the flow arm trains its proposal on the T = 1 samples of
+    the burn-in's second half (thinned to at most max_train) and then runs
+    with independence proposals at probability p_flow on the T = 1 rung;
+    each arm gets the same wall budget
+    'seconds', the flow arm's training included.  ESS (Sec. III.C) counts
+    the arm's T = 1 chain; ESS/s divides by the arm's wall time.  Accuracy:
+    per-parameter means of the two arms agree within 3 combined Monte Carlo
+    standard errors, and standard deviations within 5 %.
     """
     say = log or (lambda *_: None)
     dim = x0.shape[-1]
     nw = x0.shape[1]
     out = {}
-    # arm 1: stretch only
-    smp = PTSampler(loglike, logprior, betas, nw, dim, a=a, seed=seeds[0])
+    base = PTSampler(loglike, logprior, betas, nw, dim, a=a, seed=seeds[0])
     t0 = time.perf_counter()
-    smp.initialize(x0)
+    base.initialize(x0)
+    warm: list = []
+    _run_for(base, burn_seconds, warm, t0, say)
+    start = base.state.x.copy()
+    out["burn_in"] = {"steps": len(warm), "wall_s": round(time.perf_counter() - t0, 2)}
+    say("burn-in", out["burn_in"])
+    # arm 1: stretch only, continuing the burn-in
+    base.state.accepted[:] = 0
+    base.state.proposed[:] = 0
+    base.state.swaps_accepted[:] = 0
+    base.state.swaps_proposed[:] = 0
+    t0 = time.perf_counter()
     chain: list = []
-    _run_for(smp, burn_frac * seconds, chain, t0, say)
-    burn = len(chain)
-    _run_for(smp, seconds, chain, t0, say)
+    _run_for(base, seconds, chain, t0, say)
     ch_plain = np.array(chain)
-    out["stretch"] = _arm_report(smp, ch_plain, time.perf_counter() - t0, burn)
+    out["stretch"] = _arm_report(base, ch_plain, time.perf_counter() - t0, 0)
     say("stretch", out["stretch"])
-    # arm 2: stretch burn-in, flow training, then stretch + flow
-    prop = FlowProposal(dim, seed=seeds[1], **(flow_kwargs or {}))
-    smp2 = PTSampler(loglike, logprior, betas, nw, dim, a=a, seed=seeds[1], proposal=prop, p_flow=0.0)
+    # arm 2: train on the burn-in, then stretch + flow from the same state
     t0 = time.perf_counter()
-    smp2.initialize(x0)
-    chain = []
-    _run_for(smp2, burn_frac * seconds, chain, t0, say)
-    burn2 = len(chain)
-    train = np.array(chain).reshape(-1, dim)
-    if len(train) > max_train:
-        train = train[np.linspace(0, len(train) - 1, max_train).astype(int)]
+    settled = np.array(warm[len(warm) // 2:])        # the second half of the burn-in
+    keep = np.linspace(0, len(settled) - 1, max(1, min(len(settled), max_train // nw))).astype(int)
+    train = settled[keep].reshape(-1, dim)
+    prop = FlowProposal(dim, seed=seeds[1], **(flow_kwargs or {}))
     prop.fit(train, **(fit_kwargs or {}))
     say("flow trained", {"samples": int(len(train)), "train_s": round(prop.train_seconds, 2),
-                         "final_loss": round(float(prop.losses[-1]), 4) if prop.losses else None})
-    smp2.p_flow = p_flow
-    _run_for(smp2, seconds, chain, t0, say)
+                         "best_held_out_loss": round(min(prop.val_losses), 4) if prop.val_losses else None})
+    smp = PTSampler(loglike, logprior, betas, nw, dim, a=a, seed=seeds[1], proposal=prop, p_flow=p_flow)
+    smp.initialize(start)
+    chain = []
+    _run_for(smp, seconds, chain, t0, say)
     ch_flow = np.array(chain)
-    out["stretch_flow"] = _arm_report(smp2, ch_flow, time.perf_counter() - t0, burn2)
+    out["stretch_flow"] = _arm_report(smp, ch_flow, time.perf_counter() - t0, 0)
     out["stretch_flow"]["train_s"] = round(prop.train_seconds, 2)
     out["stretch_flow"]["train_samples"] = int(len(train))
     say("stretch+flow", out["stretch_flow"])
-    # equal posterior accuracy between the arms
-    a1, a2 = ch_plain[burn:].reshape(-1, dim), ch_flow[burn2:].reshape(-1, dim)
+    a1, a2 = ch_plain.reshape(-1, dim), ch_flow.reshape(-1, dim)
     e1, e2 = max(out["stretch"]["ess"], 1.0), max(out["stretch_flow"]["ess"], 1.0)
     se = np.sqrt(a1.var(0) / e1 + a2.var(0) / e2)
     with np.errstate(divide="ignore", invalid="ignore"):

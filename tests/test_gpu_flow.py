@@ -182,8 +182,8 @@ def test_training_recovers_a_known_gaussian(mbh):
     mu = rng.standard_normal(DIM)
     x = rng.multivariate_normal(mu, cov, 40000)
     from paper_2005_01827_amd.sampler import FlowProposal
-    prop = FlowProposal(DIM, max_batch=32768, seed=13)
-    prop.fit(x, steps=400, lr=2e-3, batch=4096, seed=14)
+    prop = FlowProposal(DIM, max_batch=32768, seed=13, defensive=0.0)
+    prop.fit(x, steps=400, lr=2e-3, batch=4096, seed=14, val_frac=0.0)
     xs, lq = prop.sample(20000, np.random.default_rng(15))
     entropy = 0.5 * DIM * (1 + math.log(2 * math.pi)) + 0.5 * np.linalg.slogdet(cov)[1]
     nll = -prop.logq(x[:20000]).mean()
@@ -193,5 +193,7 @@ def test_training_recovers_a_known_gaussian(mbh):
     assert nll < entropy + 0.05
     assert np.all(np.abs(xs.mean(0) - mu) < 6 * se)
     assert np.abs(np.cov(xs.T) - cov).max() < 0.05 * np.abs(cov).max()
-    assert np.allclose(lq, prop.logq(xs), rtol=0, atol=1e-12)
+    # log q of a draw, re-evaluated from the stored float64 point (float32
+    # standardization twice), agrees to float32 rounding
+    assert np.allclose(lq, prop.logq(xs), rtol=0, atol=1e-4)
     prop.flow.close()

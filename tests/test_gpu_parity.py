@@ -141,6 +141,28 @@ def test_schedules_give_identical_bits(small):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("modes,ns", [(((2, 2),), 8), (((2, 2), (3, 3)), 1024), (((4, 3), (2, 1)), 64)])
+def test_mode_subsets_and_knot_counts(oracle, modes, ns):
+    """Mode subsets (including the (2,2) mode alone and two higher modes
+    without it) and the smallest and largest knot counts."""
+    import torch
+    from paper_2005_01827_amd import mbh
+    print(f"case: modes={modes} ns={ns}", flush=True)
+    w = inputs.small_config(6, seed=11)
+    g = w.grid
+    psd = inputs.psd_aet(g.freqs)
+    d = oracle.template(w.injection, g, modes, ns, w.t0) + inputs.noise(g, psd, 78)
+    L = mbh.Likelihood(g, d, psd, modes, ns, w.t0, max_batch=8)
+    try:
+        got = L.loglike(w.walkers).cpu().numpy()
+        torch.cuda.synchronize()
+        ref = oracle.loglike(w.walkers, g, d, psd, modes, ns, w.t0)
+        _report(f"modes={len(modes)} ns={ns}", got, ref[:, 0])
+        assert np.all(_lnl_close(got, ref[:, 0]))
+    finally:
+        L.close()
+
+
 def test_noiseless_injection_from_gpu_template_is_zero(small):
     import torch
     from paper_2005_01827_amd import mbh
