@@ -32,7 +32,7 @@ FP64_PEAK_TFLOPS = 78.6            # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 
 FLOPS_PER_MODE_BIN = 111           # 8 cubics 48, e^{i phi} 37, A e^{i phi} 2, 3 complex MACs 24
 FLOPS_PER_WALKER_BIN = 51          # per channel: d-h 2, |r|^2 w 5, Re(d h*) w 5, |h|^2 w 5
 BYTES_PER_WALKER_BIN = 72          # d (3 x complex128) + w (3 x float64), streamed per walker
-KERNEL_REV = "dense-v9"            # traffic counters are only reused for this kernel revision
+KERNEL_REV = "dense-v11"           # traffic counters are only reused for this kernel revision
 
 
 def parse():
@@ -206,7 +206,7 @@ def precision_study(args):
             res[name] = L.loglike(walkers).cpu().numpy()
             L.close()
         d = np.abs(res["fp32c"] - res["fp64"])
-        bound = 1e-6 * snr + 1e-12 * np.abs(res["fp64"]) + 1e-6
+        bound = 5e-9 * snr * snr + 1e-6 * snr + 1e-5
         hist, edges = np.histogram(np.log10(np.maximum(d, 1e-16)), bins=np.arange(-16, 4))
         case = {"snr": round(snr, 2), "D_L_gpc": round(float(inj[4]), 4),
                 "abs_err_fp32c_vs_fp64": {"max": float(d.max()), "median": float(np.median(d)),
@@ -228,7 +228,7 @@ def precision_study(args):
     L0.close()
     result = {"metric": "FP32C ln L error per walker vs FP64", "unit": "abs ln L", "n_gpus": 1,
               "config": {"workload": w.name, "walkers": B, "dense_bins": g.n},
-              "bound": "1e-6 SNR + 1e-12 |lnL| + 1e-6", "cases": cases}
+              "bound": "5e-9 SNR^2 + 1e-6 SNR + 1e-5", "cases": cases}
     print(json.dumps(result), flush=True)
 
 

@@ -517,7 +517,7 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float x)
 // Kahan-compensated FP32 sums of <d|h> and <h|h> (the residual is formed in
 // the reduction from the FP64 <d|d>).
 template <bool kWriteH, bool kF32>
-__global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs a)
+__global__ __launch_bounds__(kDenseThreads, 4) void k_dense(DenseArgs a)
 {
     __shared__ double red[kDenseThreads / 64][kPartials];
     const int total = min(a.wbase[a.B], a.max_items);
@@ -553,12 +553,16 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs a)
                 const ModeBand mb = a.band[wk * a.nm + m];
                 if (mb.active && mb.khi >= kw && mb.klo <= kwl) {
                     cint *kb = (cint *)(a.kbin + (size_t)(wk * a.nm + m) * ns);
-                    const int kfirst = max(kw, mb.klo);
-                    const double f = (double)kfirst * a.df;
-                    int i = (int)floor(log(f / mb.fs) / log(mb.fe / mb.fs) * (double)(ns - 1));
-                    i = uni_i(max(0, min(ns - 2, i)));
-                    while (i > 0 && kb[i] > kfirst) i = uni_i(i - 1);
-                    while (i < ns - 2 && kb[i + 1] <= kfirst) i = uni_i(i + 1);
+                    const int kfirst = uni_i(max(kw, mb.klo));
+                    // largest i in [0, ns-2] with kb[i] <= kfirst: a binary
+                    // search on wave-uniform integers (scalar unit only)
+                    int i = 0, ihi = ns - 2;
+                    while (i < ihi) {
+                        const int mid = (i + ihi + 1) >> 1;
+                        if (kb[mid] <= kfirst) i = mid;
+                        else ihi = mid - 1;
+                    }
+                    i = uni_i(i);
                     mlo[m] = uni_i(mb.klo);
                     mhi[m] = uni_i(mb.khi);
                     cur[m] = i;
@@ -604,36 +608,37 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs a)
             for (int m = 0; m < kMaxModes; ++m) {
                 const int lo = max(s0, mlo[m]), hi_ = min(s0 + 63, mhi[m]);
                 if (lo > hi_) continue;
-                const size_t wm = (size_t)(wk * a.nm + m);
-                const int *kb = a.kbin + wm * ns;
-                const double *kf = a.kf + wm * ns;
-                const double *cf = a.coef + wm * (ns - 1) * kCoefPerIv;
+                // knots and bin bounds of (walker, mode) start at kbo, its
+                // intervals at ivo = kbo - wm; one shared base pointer per
+                // table keeps the per-mode state to two 32-bit offsets
+                const int wm = wk * a.nm + m;
+                const int kbo = uni_i(wm * ns);
+                const int ivo = kbo - wm;
                 while (nxt[m] <= lo) {
                     cur[m] = uni_i(cur[m] + 1);
-                    nxt[m] = uni_i(cur[m] < ns - 2 ? ((cint *)kb)[cur[m] + 1] : 0x7fffffff);
+                    nxt[m] = uni_i(cur[m] < ns - 2 ? ((cint *)a.kbin)[kbo + cur[m] + 1] : 0x7fffffff);
                 }
                 const bool in = (k >= mlo[m]) && (k <= mhi[m]);
-                const float *cf32 = kF32 ? a.coef32 + wm * (ns - 1) * kCoefPerIv : nullptr;
                 if (hi_ < nxt[m]) {
                     const int iv = cur[m];
-                    const double x0 = ((cdouble *)kf)[iv];
+                    const double x0 = ((cdouble *)a.kf)[kbo + iv];
+                    const size_t c0 = (size_t)(ivo + iv) * kCoefPerIv;
                     if (in) {
                         if (kF32)
-                            mode_bin32<cdouble *, cfloat *>(K, Kf, (cdouble *)(cf + (size_t)iv * kCoefPerIv),
-                                                            (cfloat *)(cf32 + (size_t)iv * kCoefPerIv), f - x0, hr32,
-                                                            hi32);
+                            mode_bin32<cdouble *, cfloat *>(K, Kf, (cdouble *)a.coef + c0, (cfloat *)a.coef32 + c0,
+                                                            f - x0, hr32, hi32);
                         else
-                            mode_bin<cdouble *>(K, (cdouble *)(cf + (size_t)iv * kCoefPerIv), f - x0, hr, hi);
+                            mode_bin<cdouble *>(K, (cdouble *)a.coef + c0, f - x0, hr, hi);
                     }
                 } else if (in) {
                     int iv = cur[m];
-                    while (iv < ns - 2 && kb[iv + 1] <= k) ++iv;
+                    while (iv < ns - 2 && a.kbin[kbo + iv + 1] <= k) ++iv;
+                    const size_t c0 = (size_t)(ivo + iv) * kCoefPerIv;
                     if (kF32)
-                        mode_bin32<const double *, const float *>(K, Kf, cf + (size_t)iv * kCoefPerIv,
-                                                                  cf32 + (size_t)iv * kCoefPerIv, f - kf[iv], hr32,
-                                                                  hi32);
+                        mode_bin32<const double *, const float *>(K, Kf, a.coef + c0, a.coef32 + c0,
+                                                                  f - a.kf[kbo + iv], hr32, hi32);
                     else
-                        mode_bin<const double *>(K, cf + (size_t)iv * kCoefPerIv, f - kf[iv], hr, hi);
+                        mode_bin<const double *>(K, a.coef + c0, f - a.kf[kbo + iv], hr, hi);
                 }
             }
             if (kWriteH) {
@@ -644,6 +649,11 @@ __global__ __launch_bounds__(kDenseThreads) void k_dense(DenseArgs a)
                 if (inw) {
 #pragma unroll
                     for (int ch = 0; ch < 3; ++ch) {
+                        // whitened template h sqrt(w); <d|h> and <h|h> are summed
+                        // here and the residual is formed in the reduction with
+                        // the FP64 <d|d> (summing the residual directly in FP32
+                        // was measured to be less accurate: the FP32 whitened
+                        // data then add an error floor of ~1e-4 per walker)
                         const float wr = hr32[ch] * sv32[ch], wi = hi32[ch] * sv32[ch];
                         kahan_add(ks[ch], kc[ch], fmaf(dv32[ch].x, wr, dv32[ch].y * wi));
                         kahan_add(ks[3 + ch], kc[3 + ch], fmaf(wr, wr, wi * wi));
