@@ -185,7 +185,9 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
     c->g.precision = desc->precision;
     c->max_batch = desc->max_batch;
     c->precision = desc->precision;
-    const long long ntile_max = (n + kTileBins - 1) / kTileBins + 1;
+    c->g.steps = dense_steps(n, desc->max_batch);
+    c->g.tile_bins = kDenseThreads * c->g.steps;
+    const long long ntile_max = (n + c->g.tile_bins - 1) / c->g.tile_bins + 1;
     const long long items = (long long)desc->max_batch * ntile_max;
     if (items > 0x7fffffffLL) { delete c; return MBH_EINVAL; }
     c->max_items = (int)items;

@@ -6,7 +6,7 @@
 // over each walker's union band, plus the data-only sum outside it from
 // per-channel prefix sums, so that ln L = -(R + DD_out)/2.
 //
-// Work decomposition: the dense grid is cut into tiles of kTileBins bins;
+// Work decomposition: the dense grid is cut into tiles of tile_bins bins;
 // work items (walker, tile) cover each walker's union band and are listed
 // tile-major (all walkers of tile 0, then tile 1, ...) for a grid-stride
 // loop, so that workgroups running together share a few data tiles in L2.
@@ -144,8 +144,8 @@ __global__ void k_walker_bands(int B, int nm, GridDesc g, const Source *__restri
         if (hi >= lo) {
             r.klo = lo;
             r.khi = hi;
-            r.tile_lo = (lo - g.k0) / kTileBins;
-            r.ntiles = (hi - g.k0) / kTileBins - r.tile_lo + 1;
+            r.tile_lo = (lo - g.k0) / g.tile_bins;
+            r.ntiles = (hi - g.k0) / g.tile_bins - r.tile_lo + 1;
         }
     }
     wb[w] = r;
@@ -262,6 +262,7 @@ __global__ __launch_bounds__(256) void k_tile_fill(int B, const WalkerBand *__re
 // ---------------------------------------------------------------------------
 struct DenseArgs {
     int B, nm, ns, k0, n;
+    int steps, tile_bins;
     double df;
     int max_items;
     int one_per_walker;
@@ -538,8 +539,8 @@ __global__ __launch_bounds__(kDenseThreads, 4) void k_dense(DenseArgs a)
         const WalkerBand wb = a.wband[wk];
         const int tile = a.one_per_walker ? wb.tile_lo + (item - a.wbase[wk]) : uni_i(a.item_t[item]);
         const int slot = a.wbase[wk] + (tile - wb.tile_lo);
-        const int kw = uni_i(a.k0 + tile * kTileBins + wave * (64 * kDenseJ));
-        const int kwl = kw + 64 * kDenseJ - 1;
+        const int kw = uni_i(a.k0 + tile * a.tile_bins + wave * (64 * a.steps));
+        const int kwl = kw + 64 * a.steps - 1;
 
         // per-mode wave-uniform state: band, current interval, next bound
         int mlo[kMaxModes], mhi[kMaxModes], cur[kMaxModes], nxt[kMaxModes];
@@ -578,7 +579,7 @@ __global__ __launch_bounds__(kDenseThreads, 4) void k_dense(DenseArgs a)
 #pragma unroll
         for (int q = 0; q < 6; ++q) ks[q] = kc[q] = 0.0f;
 
-        for (int j = 0; j < kDenseJ; ++j) {
+        for (int j = 0; j < a.steps; ++j) {
             const int s0 = kw + 64 * j;
             const int k = s0 + lane;
             const bool inw = (k >= wb.klo) && (k <= wb.khi);
@@ -761,6 +762,8 @@ DenseArgs make_args(int B, const Modes &md, const GridDesc &g, const Work &wk, c
     a.ns = g.ns;
     a.k0 = g.k0;
     a.n = g.n;
+    a.steps = g.steps;
+    a.tile_bins = g.tile_bins;
     a.df = g.df;
     a.max_items = max_items;
     a.one_per_walker = 0;
@@ -856,7 +859,7 @@ hipError_t launch_walker_bands(int B, const Modes &md, const GridDesc &g, const 
 
 void launch_items(int B, const GridDesc &g, const Work &wk, int max_items, hipStream_t st)
 {
-    const int ntiles = (g.n + kTileBins - 1) / kTileBins;
+    const int ntiles = (g.n + g.tile_bins - 1) / g.tile_bins;
     k_tile_count<<<ntiles, 256, 0, st>>>(B, wk.wband, wk.tile_off);
     k_tile_scan<<<1, 1024, 0, st>>>(ntiles, wk.tile_off);
     k_tile_fill<<<ntiles, 256, 0, st>>>(B, wk.wband, wk.tile_off, wk.item_w, wk.item_t, max_items);
@@ -901,7 +904,7 @@ hipError_t launch_template(const Modes &md, const GridDesc &g, const Work &wk, d
     Data none = {nullptr, nullptr, nullptr, nullptr, nullptr};
     const long long nh = 3LL * g.n;
     k_zero2<<<(unsigned)((nh + 255) / 256), 256, 0, st>>>(h, nh);
-    const int max_items = (g.n + kTileBins - 1) / kTileBins + 1;
+    const int max_items = (g.n + g.tile_bins - 1) / g.tile_bins + 1;
     launch_items(1, g, wk, max_items, st);
     DenseArgs a = make_args(1, md, g, wk, none, max_items);
     a.h = h;

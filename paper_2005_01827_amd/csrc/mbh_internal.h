@@ -14,12 +14,18 @@ constexpr int kNumFn = 8;          // A, phi, Re/Im T^A, Re/Im T^E, Re/Im T^T
 constexpr int kCoefPerIv = kNumFn * 4;  // 32 doubles per sparse interval
 
 // Dense tiling of the frequency axis: a work item is (walker, tile) with
-// kTileBins consecutive bins, processed by kDenseThreads threads; each
-// wavefront takes 64*kDenseJ consecutive bins in kDenseJ steps of 64
-// (coalesced loads of d and w).
+// GridDesc::tile_bins = kDenseThreads * GridDesc::steps consecutive bins,
+// processed by kDenseThreads threads; each wavefront takes 64*steps
+// consecutive bins in 'steps' steps of 64 (coalesced loads of d and w).
+// Long tiles let a wavefront reuse each interval's coefficients from the
+// scalar cache over many steps (measured on a 1024-walker sweep of the
+// 2^25-s grid: 8 steps 18.1 ms, 16 steps 16.8 ms, 32 steps 16.3 ms, 64 steps
+// 16.8 ms, where coarser items balance worse); small problems need shorter
+// tiles to keep enough work items in flight, so a context picks 'steps' from
+// its grid and batch size (dense_steps()).
 constexpr int kDenseThreads = 256;
-constexpr int kDenseJ = 8;
-constexpr int kTileBins = kDenseThreads * kDenseJ;
+constexpr int kMaxDenseSteps = 32;
+constexpr int kMinDenseSteps = 4;
 constexpr int kPartials = 9;       // R_c, DH_c, HH_c for c = A, E, T
 
 // Per-walker constants of the waveform model (built by the source kernel).
@@ -64,7 +70,19 @@ struct GridDesc {
     int n;
     int ns;             // sparse knots per mode
     int precision;      // 0: FP64 dense stage; 1: FP32 with compensated sums
+    int steps;          // 64-bin steps per wavefront in the dense stage
+    int tile_bins;      // kDenseThreads * steps
 };
+
+// Steps per wavefront for a grid of n bins and batches up to max_batch: the
+// longest tile (up to kMaxDenseSteps) that still gives about 4096 work items
+// for a full batch, at least kMinDenseSteps.
+inline int dense_steps(long long n, int max_batch)
+{
+    int s = kMaxDenseSteps;
+    while (s > kMinDenseSteps && (long long)max_batch * n < 4096LL * kDenseThreads * s) s /= 2;
+    return s;
+}
 
 // Device workspace of a context (all pointers device memory).
 struct Work {
