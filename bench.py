@@ -305,7 +305,7 @@ def main():
         try:
             tj = json.load(open(args.traffic_json))
             if tj.get("config") == args.config and tj.get("walkers") == B and tj.get("kernel_rev") == KERNEL_REV:
-                traffic = tj.get("hbm_bytes_per_launch")
+                traffic = tj.get("hbm_bytes_per_launch_by_blocks_per_cu", {}).get(str(bpc))
         except Exception:
             traffic = None
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -147,87 +147,154 @@ __global__ void k_response(int B, Modes md, GridDesc g, const Source *__restrict
 // One thread per (walker, mode, function): not-a-knot spline through
 // (f_j, y_j).  Unknowns M_1..M_{ns-2} (second derivatives); M_0 and M_{ns-1}
 // follow from continuity of the third derivative at f_1 and f_{ns-2}.
-// scratch holds 2*ns doubles per thread.  The q = 0 thread of each
-// (walker, mode) also writes kbin[i], the first dense bin k with
-// k df >= f_i, so that the dense stage can find intervals by integer
-// comparison: bin k lies in interval i iff kbin[i] <= k < kbin[i+1], which
-// is the same as f_i <= k df < f_{i+1} in double precision.
+// The Thomas sweep keeps 2*ns doubles per thread in scratch, interleaved
+// across threads (element r of thread id at r*nt + id) so that the 64 lanes
+// of a wavefront touch consecutive addresses.  Each of the three serial
+// sweeps loads kSplineU knots' operands at once and then runs kSplineU steps
+// from registers, so a step waits on memory once per kSplineU steps rather
+// than once per step.  The kNumFn threads of each (walker, mode) also write
+// kbin[i] for i = q mod kNumFn: the first dense bin k with k df >= f_i, so
+// that the dense stage can find intervals by integer comparison: bin k lies
+// in interval i iff kbin[i] <= k < kbin[i+1], which is the same as
+// f_i <= k df < f_{i+1} in double precision.
+constexpr int kSplineU = 16;
+
 __global__ void k_spline(int B, Modes md, GridDesc g, const ModeBand *__restrict__ band,
                          const double *__restrict__ kf, const double *__restrict__ fn, double *__restrict__ coef,
                          double *__restrict__ scratch, int *__restrict__ kbin)
 {
+    constexpr int U = kSplineU;
     const int ns = g.ns;
+    const int nt = B * md.nm * kNumFn;
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= B * md.nm * kNumFn) return;
+    if (id >= nt) return;
     const int q = id % kNumFn;
     const int wm = id / kNumFn;
     double *out = coef + (size_t)wm * (ns - 1) * kCoefPerIv + q * 4;
-    if (q == 0) {
-        const double *x = kf + (size_t)wm * ns;
+    const double *x = kf + (size_t)wm * ns;
+    const bool act = band[wm].active != 0;
+    {
         int *kb = kbin + (size_t)wm * ns;
-        const bool act = band[wm].active != 0;
-        for (int i = 0; i < ns; ++i) {
-            long long k = act ? (long long)ceil(x[i] / g.df) : 0;
-            if (act) {
-                while ((double)k * g.df < x[i]) ++k;
-                while ((double)(k - 1) * g.df >= x[i]) --k;
+        for (int i0 = q; i0 < ns; i0 += U * kNumFn) {
+            double xs[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) xs[u] = x[min(i0 + u * kNumFn, ns - 1)];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * kNumFn;
+                if (i < ns) {
+                    // ceil of the rounded quotient is within one of the first k
+                    // with k df >= f (|f/df| < 2^31, quotient error < 1e-6), so one
+                    // correction each way makes it exact
+                    long long k = act ? (long long)ceil(xs[u] / g.df) : 0;
+                    if (act) {
+                        if ((double)k * g.df < xs[u]) ++k;
+                        if ((double)(k - 1) * g.df >= xs[u]) --k;
+                    }
+                    kb[i] = (int)max(-1LL, min(k, 0x7ffffffeLL));
+                }
             }
-            kb[i] = (int)max(-1LL, min(k, 0x7ffffffeLL));
         }
     }
-    if (!band[wm].active) {
+    if (!act) {
         for (int i = 0; i < ns - 1; ++i)
             for (int c = 0; c < 4; ++c) out[(size_t)i * kCoefPerIv + c] = 0.0;
         return;
     }
-    const double *x = kf + (size_t)wm * ns;
     const double *y = fn + ((size_t)wm * kNumFn + q) * ns;
-    double *cp = scratch + (size_t)id * 2 * ns;
-    double *Mv = cp + ns;
+    double *cp = scratch + id;                    // cp[r]  -> cp[r * nt]
+    double *Mv = scratch + (size_t)ns * nt + id;  // Mv[i]  -> Mv[i * nt]
     const int m = ns - 2;  // unknowns M_1..M_{ns-2}, row r <-> M_{r+1}
 
-    // forward elimination
+    // forward elimination; row r uses knots r, r+1, r+2
     double prev_c = 0.0, prev_d = 0.0;
-    for (int r = 0; r < m; ++r) {
-        const int i = r + 1;
-        const double h0 = x[i] - x[i - 1], h1 = x[i + 1] - x[i];
-        const double s0 = (y[i] - y[i - 1]) / h0, s1 = (y[i + 1] - y[i]) / h1;
-        double sub = h0, dia = 2.0 * (h0 + h1), sup = h1;
-        const double rhs = 6.0 * (s1 - s0);
-        if (r == 0) {
-            dia = (h0 + h1) * (h0 + 2.0 * h1) / h1;
-            sup = (h1 * h1 - h0 * h0) / h1;
-            sub = 0.0;
+    double xa = x[0], xb = x[1], ya = y[0], yb = y[1];
+    for (int r0 = 0; r0 < m; r0 += U) {
+        double xs[U], ys[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = min(r0 + u + 2, ns - 1);
+            xs[u] = x[j];
+            ys[u] = y[j];
         }
-        if (r == m - 1) {
-            dia = (h0 + h1) * (2.0 * h0 + h1) / h0;
-            sub = (h0 * h0 - h1 * h1) / h0;
-            sup = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = r0 + u;
+            if (r >= m) continue;
+            const double xc = xs[u], yc = ys[u];
+            const double h0 = xb - xa, h1 = xc - xb;
+            const double s0 = (yb - ya) / h0, s1 = (yc - yb) / h1;
+            double sub = h0, dia = 2.0 * (h0 + h1), sup = h1;
+            const double rhs = 6.0 * (s1 - s0);
+            if (r == 0) {
+                dia = (h0 + h1) * (h0 + 2.0 * h1) / h1;
+                sup = (h1 * h1 - h0 * h0) / h1;
+                sub = 0.0;
+            }
+            if (r == m - 1) {
+                dia = (h0 + h1) * (2.0 * h0 + h1) / h0;
+                sub = (h0 * h0 - h1 * h1) / h0;
+                sup = 0.0;
+            }
+            const double den = dia - sub * prev_c;
+            const double c = sup / den;
+            const double d = (rhs - sub * prev_d) / den;
+            cp[(size_t)r * nt] = c;
+            Mv[(size_t)(r + 1) * nt] = d;   // holds d_r until back substitution
+            prev_c = c;
+            prev_d = d;
+            xa = xb; xb = xc; ya = yb; yb = yc;
         }
-        const double den = dia - sub * prev_c;
-        const double c = sup / den;
-        const double d = (rhs - sub * prev_d) / den;
-        cp[r] = c;
-        Mv[r + 1] = d;   // holds d_r until back substitution
-        prev_c = c;
-        prev_d = d;
     }
-    // back substitution: M_{r+1} = d_r - c_r M_{r+2}
-    for (int r = m - 2; r >= 0; --r) Mv[r + 1] = Mv[r + 1] - cp[r] * Mv[r + 2];
+    // back substitution: M_{m} = d_{m-1}; M_{r+1} = d_r - c_r M_{r+2} for r = m-2 .. 0
+    double mn = prev_d;
+    for (int r0 = m - 2; r0 >= 0; r0 -= U) {
+        double ds[U], cs[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = max(r0 - u, 0);
+            ds[u] = Mv[(size_t)(r + 1) * nt];
+            cs[u] = cp[(size_t)r * nt];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = r0 - u;
+            if (r < 0) continue;
+            mn = ds[u] - cs[u] * mn;
+            Mv[(size_t)(r + 1) * nt] = mn;
+        }
+    }
     {
         const double h0 = x[1] - x[0], h1 = x[2] - x[1];
-        Mv[0] = ((h0 + h1) * Mv[1] - h0 * Mv[2]) / h1;
+        Mv[0] = ((h0 + h1) * Mv[(size_t)nt] - h0 * Mv[(size_t)2 * nt]) / h1;
         const double ha = x[ns - 2] - x[ns - 3], hb = x[ns - 1] - x[ns - 2];
-        Mv[ns - 1] = ((ha + hb) * Mv[ns - 2] - hb * Mv[ns - 3]) / ha;
+        Mv[(size_t)(ns - 1) * nt] = ((ha + hb) * Mv[(size_t)(ns - 2) * nt] - hb * Mv[(size_t)(ns - 3) * nt]) / ha;
     }
-    for (int i = 0; i < ns - 1; ++i) {
-        const double h = x[i + 1] - x[i];
-        const double sl = (y[i + 1] - y[i]) / h;
-        double *o = out + (size_t)i * kCoefPerIv;
-        o[0] = y[i];
-        o[1] = sl - h * (2.0 * Mv[i] + Mv[i + 1]) / 6.0;
-        o[2] = 0.5 * Mv[i];
-        o[3] = (Mv[i + 1] - Mv[i]) / (6.0 * h);
+    // coefficients of interval i from knots i, i+1
+    double x0 = x[0], y0 = y[0], m0 = Mv[0];
+    for (int i0 = 0; i0 < ns - 1; i0 += U) {
+        double xs[U], ys[U], ms[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = min(i0 + u + 1, ns - 1);
+            xs[u] = x[j];
+            ys[u] = y[j];
+            ms[u] = Mv[(size_t)j * nt];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u;
+            if (i >= ns - 1) continue;
+            const double x1 = xs[u], y1 = ys[u], m1 = ms[u];
+            const double h = x1 - x0;
+            const double sl = (y1 - y0) / h;
+            double *o = out + (size_t)i * kCoefPerIv;
+            o[0] = y0;
+            o[1] = sl - h * (2.0 * m0 + m1) / 6.0;
+            o[2] = 0.5 * m0;
+            o[3] = (m1 - m0) / (6.0 * h);
+            x0 = x1; y0 = y1; m0 = m1;
+        }
     }
 }
 
