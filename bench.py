@@ -32,7 +32,7 @@ FP64_PEAK_TFLOPS = 78.6            # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 
 FLOPS_PER_MODE_BIN = 111           # 8 cubics 48, e^{i phi} 37, A e^{i phi} 2, 3 complex MACs 24
 FLOPS_PER_WALKER_BIN = 51          # per channel: d-h 2, |r|^2 w 5, Re(d h*) w 5, |h|^2 w 5
 BYTES_PER_WALKER_BIN = 72          # d (3 x complex128) + w (3 x float64), streamed per walker
-KERNEL_REV = "dense-v13"           # traffic counters are only reused for this kernel revision
+KERNEL_REV = "dense-v14"           # traffic counters are only reused for this kernel revision
 
 
 def parse():
@@ -51,6 +51,8 @@ def parse():
                          "stretch + flow, SECONDS of wall time per arm; prints one JSON line")
     ap.add_argument("--sampler-burn", type=float, default=60.0, metavar="SECONDS",
                     help="shared stretch-only burn-in before the two arms of --sampler")
+    ap.add_argument("--sampler-save", default="", metavar="NPZ",
+                    help="with --sampler: save both arms' T = 1 chains (every 5th step, float32)")
     ap.add_argument("--sampler-walkers", type=int, default=512)
     ap.add_argument("--sampler-rungs", type=int, default=8)
     ap.add_argument("--schedule-study", action="store_true",
@@ -117,7 +119,12 @@ def sampler_comparison(args):
     log = lambda name, rep: print(f"# {name}: {json.dumps(rep)}", file=sys.stderr, flush=True)
     rep = S.ess_comparison(S.gpu_loglike(L), S.box_logprior(), x0, S.ladder(nt), args.sampler,
                            args.sampler_burn, seeds=(5, 55), a=1.15, log=log,
-                           fit_kwargs={"steps": 800, "lr": 2e-3, "batch": 4096})
+                           fit_kwargs={"steps": 800, "lr": 2e-3, "batch": 4096},
+                           keep_chains=bool(args.sampler_save))
+    if args.sampler_save:
+        ch_plain, ch_flow = rep.pop("chains")
+        np.savez_compressed(args.sampler_save, stretch=ch_plain[::5].astype(np.float32),
+                            stretch_flow=ch_flow[::5].astype(np.float32))
     torch.cuda.synchronize()
     result = {"metric": "ESS/s at T = 1, stretch + learned proposal vs stretch only", "unit": "ESS/s",
               "value": rep["stretch_flow"]["ess_per_s"], "baseline_value": rep["stretch"]["ess_per_s"],
@@ -148,7 +155,7 @@ def schedule_study(args):
     out = torch.empty(B, dtype=torch.float64, device="cuda")
     ref = None
     times = {}
-    shapes = [(b, False) for b in (1, 2, 4, 6, 8, 12, 16)] + [(1, True)]
+    shapes = [(b, False) for b in (1, 2, 3, 4, 6, 8, 9, 12, 16, 24, 32)] + [(1, True)]
     for bpc, one in shapes:
         L.set_schedule(bpc, one)
         L.set_timing(True)

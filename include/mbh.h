@@ -152,9 +152,10 @@ mbh_status mbh_get_schedule(const mbh_ctx *ctx, int *blocks_per_cu, int *one_per
 
 /* Autotuner: run the sparse stages once for params_dev[B][11] (device,
  * 1 <= B <= max_batch), time the dense kernel with HIP events for every
- * blocks_per_cu in {2, 4, 6, 8, 12, 16} (median of reps in 1..100 launches),
- * and keep the fastest as the context's tiled schedule.  best_bpc_host and
- * best_ms_host (may be NULL) receive the choice and its median time [ms].
+ * blocks_per_cu in {2, 3, 4, 6, 8, 9, 12, 16, 24, 32} (median of reps in
+ * 1..100 launches), and keep the fastest as the context's tiled schedule.
+ * best_bpc_host and best_ms_host (may be NULL) receive the choice and its
+ * median time [ms].
  * Synchronous on 'stream'. */
 mbh_status mbh_autotune(mbh_ctx *ctx, const double *params_dev, int B, int reps, int *best_bpc_host,
                         double *best_ms_host, void *stream);

@@ -224,7 +224,7 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
     TRY(dalloc(c, &c->wk.wbase, (size_t)B + 1));
     TRY(dalloc(c, &c->wk.partial, (size_t)c->max_items * kPartials));
     TRY(dalloc(c, &c->wk.out7, (size_t)B * 7));
-    TRY(dalloc(c, &c->wk.cis_tab, (size_t)32));
+    TRY(dalloc(c, &c->wk.cis_tab, (size_t)kCisTabDoubles));
     TRY(dalloc(c, &c->wk.cis32, (size_t)32));
     if (desc->precision == MBH_FP32C) {
         TRY(dalloc(c, &c->dw32, (size_t)3 * n));
@@ -435,7 +435,7 @@ mbh_status mbh_autotune(mbh_ctx *ctx, const double *params_dev, int B, int reps,
         (void)hipEventDestroy(e0);
         return hip_fail(ctx, e, "event create");
     }
-    static const int kCand[] = {2, 4, 6, 8, 12, 16};
+    static const int kCand[] = {2, 3, 4, 6, 8, 9, 12, 16, 24, 32};
     int best = ctx->sch.blocks_per_cu;
     double best_ms = 1e300;
     for (int c : kCand) {

@@ -288,28 +288,38 @@ struct DenseArgs {
 
 __device__ __forceinline__ int uni_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// e^{i phi}: phi = q pi/2 + r with |r| <= pi/4 (two-constant FMA reduction),
-// then Taylor polynomials of sin r (to r^15) and cos r (to r^16), whose
-// truncation errors are below 5e-17 on |r| <= pi/4, and the quadrant q mod 4.
-// The 17 constants come from a small device table (filled once per context)
-// read through the constant address space, so they sit in scalar registers
-// and every Horner step is one three-operand FMA; compile-time literals end
-// up in vector registers, copied before each accumulate-form FMA.
-constexpr int kCisN = 17;
+// e^{i phi} = e^{i q pi/32} e^{i r}.  t = phi 32/pi is rounded to the
+// integer q by adding and subtracting 1.5 2^52 (exact for |t| < 2^51), which
+// leaves q mod 2^32 in the low word of the sum; r = phi - q pi/32 with a
+// two-part pi/32 (two FMAs), so |r| <= pi/64 up to rounding.  On that range
+// the Taylor polynomials of sin r (to r^7) and cos r (to r^8) truncate below
+// 5e-18, and e^{i q pi/32} is entry q mod 64 of a table of cos and sin of
+// j pi/32, staged in LDS: one per-lane LDS read replaces the quadrant logic
+// and most of the polynomial of a reduction modulo pi/2.
+//
+// Device table layout (filled once per context): kCisN constants, then the
+// kRotN (cos, sin) pairs.
+constexpr int kRotN = 64;
+constexpr int kCisN = 12;
+constexpr int kTwoOverPi = 10;   // 2/pi, for the quarter-turn reduction of the FP32 stage
+constexpr double kRoundShift = 6755399441055744.0;   // 1.5 * 2^52
+static_assert(kCisN % 2 == 0 && kCisN + 2 * kRotN <= kCisTabDoubles, "rotation table must fit the device table");
 const double kCisHost[kCisN] = {
-    0.63661977236758134308,        // 2/pi
-    1.5707963267948965580,         // pi/2 rounded to double
-    6.123233995736766036e-17,      // pi/2 - the above
-    -1.0 / 1307674368000.0, 1.0 / 6227020800.0, -1.0 / 39916800.0, 1.0 / 362880.0,
-    -1.0 / 5040.0, 1.0 / 120.0, -1.0 / 6.0,                                   // sin: r^15 .. r^3
-    1.0 / 20922789888000.0, -1.0 / 87178291200.0, 1.0 / 479001600.0, -1.0 / 3628800.0,
-    1.0 / 40320.0, -1.0 / 720.0, 1.0 / 24.0};                                 // cos: r^16 .. r^4
+    10.185916357881301489,                                    // 32/pi
+    3.141592653589793116 / 32.0,                              // pi/32 rounded to double (exact scaling of pi)
+    1.2246467991473532e-16 / 32.0,                            // pi/32 - the above
+    -1.0 / 5040.0, 1.0 / 120.0, -1.0 / 6.0,                   // sin: r^7 .. r^3
+    1.0 / 40320.0, -1.0 / 720.0, 1.0 / 24.0, -0.5,            // cos: r^8 .. r^2
+    0.63661977236758134308,                                   // 2/pi
+    0.0};
 
 typedef const __attribute__((address_space(4))) double cdouble;
 typedef const __attribute__((address_space(4))) int cint;
 
 struct CisConst {
-    double k[kCisN];
+    double k[kTwoOverPi];
+    double two_over_pi;
+    const double2 *rot;   // kRotN entries in LDS
 };
 
 // A zero the compiler cannot prove wave-uniform: indexing with it turns a
@@ -321,37 +331,39 @@ __device__ __forceinline__ int lane_zero()
     return z;
 }
 
-// The sin/cos constants are held in VGPRs (34 of them): in scalar registers
-// they pushed the per-mode interval state and the coefficient blocks into
-// SGPR spills, whose reloads cost more VALU issue than the VGPRs cost
-// occupancy (measured: 20.4 ms against 23.3 ms for a 1024-walker sweep).
-__device__ __forceinline__ void load_cis(CisConst &K, const double *tab)
+// The polynomial and reduction constants are held in VGPRs (20 of them): in
+// scalar registers they pushed the per-mode interval state and the
+// coefficient blocks into SGPR spills, whose reloads cost more VALU issue
+// than the VGPRs cost occupancy.  The rotation table is copied to LDS by the
+// workgroup (the caller synchronises before first use).
+__device__ __forceinline__ void load_cis(CisConst &K, const double *tab, double2 *rot_lds)
 {
     const double *t = tab + lane_zero();
 #pragma unroll
-    for (int i = 0; i < kCisN; ++i) K.k[i] = t[i];
+    for (int i = 0; i < kTwoOverPi; ++i) K.k[i] = t[i];
+    K.two_over_pi = t[kTwoOverPi];
+    for (int i = threadIdx.x; i < kRotN; i += blockDim.x)
+        rot_lds[i] = ((const double2 *)(tab + kCisN))[i];
+    K.rot = rot_lds;
 }
 
 __device__ __forceinline__ void cis(const CisConst &K, double phi, double &sn, double &cs)
 {
-    const double q = rint(phi * K.k[0]);
+    const double y = fma(phi, K.k[0], kRoundShift);
+    const double q = y - kRoundShift;
+    const double2 e = K.rot[__double2loint(y) & (kRotN - 1)];
     double r = fma(-q, K.k[1], phi);
     r = fma(-q, K.k[2], r);
     const double r2 = r * r;
     double ps = fma(K.k[3], r2, K.k[4]);
-#pragma unroll
-    for (int i = 5; i <= 9; ++i) ps = fma(ps, r2, K.k[i]);
+    ps = fma(ps, r2, K.k[5]);
     const double sr = fma(r * r2, ps, r);
-    double pc = fma(K.k[10], r2, K.k[11]);
-#pragma unroll
-    for (int i = 12; i <= 16; ++i) pc = fma(pc, r2, K.k[i]);
-    pc = fma(pc, r2, -0.5);
+    double pc = fma(K.k[6], r2, K.k[7]);
+    pc = fma(pc, r2, K.k[8]);
+    pc = fma(pc, r2, K.k[9]);
     const double cr = fma(r2, pc, 1.0);
-    const int iq = ((int)q) & 3;
-    const double a = (iq & 1) ? cr : sr;   // sin for even q, cos for odd q
-    const double b = (iq & 1) ? sr : cr;
-    sn = (iq & 2) ? -a : a;
-    cs = ((iq + 1) & 2) ? -b : b;
+    cs = fma(e.x, cr, -(e.y * sr));
+    sn = fma(e.y, cr, e.x * sr);
 }
 
 // Cubic c0 + c1 x + c2 x^2 + c3 x^3 from a wave-uniform table (scalar
@@ -365,9 +377,17 @@ __device__ __forceinline__ void cis(const CisConst &K, double phi, double &sn, d
 // the product c3 * x from a scalar register was measured to drop the c3 x^3
 // term on gfx950 when x had just been computed (reproduced by a one-wavefront
 // test kernel), so that form is not used; the parity tests guard this.
+// The copy of c2 is one 64-bit move (the compiler splits it into two 32-bit
+// moves).
+__device__ __forceinline__ double vcopy(double s)
+{
+    double v;
+    asm("v_mov_b64 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
 __device__ __forceinline__ double cubic_s(cdouble *c, double x)
 {
-    const double u = fma(-c[3], x, -c[2]);
+    const double u = fma(-c[3], x, -vcopy(c[2]));
     const double v = fma(u, x, -c[1]);
     return fma(-v, x, c[0]);
 }
@@ -407,6 +427,40 @@ __device__ __forceinline__ void mode_bin(const CisConst &K, P c, double dx, doub
     }
 }
 
+// One mode at the NB bins of a lane in one step, all in one interval: the
+// wave-uniform coefficients are read once and feed NB independent
+// evaluations.  A bin outside the mode's band contributes through a zero
+// amplitude instead of a branch, so the scalar loads stay shared (its
+// offset from the knot is at most one step outside the interval, where the
+// cubics are finite).
+template <int NB>
+__device__ __forceinline__ void mode_bins_u(const CisConst &K, cdouble *c, const double (&dx)[NB],
+                                            const bool (&in)[NB], double (&hr)[NB][3], double (&hi)[NB][3])
+{
+    double ar[NB], ai[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const double amp = in[b] ? cubic_s(c + 0, dx[b]) : 0.0;
+        const double ph = cubic_s(c + 4, dx[b]);
+        double sn, cs;
+        cis(K, ph, sn, cs);
+        ar[b] = amp * cs;
+        ai[b] = amp * sn;
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const double tr = cubic_s(c + 8 + 8 * ch, dx[b]);
+            const double ti = cubic_s(c + 12 + 8 * ch, dx[b]);
+            hr[b][ch] = fma(tr, ar[b], fma(-ti, ai[b], hr[b][ch]));
+            hi[b][ch] = fma(tr, ai[b], fma(ti, ar[b], hi[b][ch]));
+        }
+        asm volatile("" ::: "memory");
+    }
+}
+
 // ---- FP32 dense stage ---------------------------------------------------
 // The phase polynomial is evaluated and reduced in FP64 (phases reach 1e7
 // rad); the remainder of a quarter turn, |r| <= pi/4, goes to FP32 for the
@@ -436,7 +490,7 @@ __device__ __forceinline__ void load_cis32(CisConst32 &K, const float *tab)
 // cos r (to r^10), truncation below 2e-9 on |r| <= pi/4.
 __device__ __forceinline__ void cis32(const CisConst &K, const CisConst32 &Kf, double phi, float &sn, float &cs)
 {
-    const double t = phi * K.k[0];
+    const double t = phi * K.two_over_pi;
     const double q = rint(t);
     const float r = (float)(t - q) * Kf.k[0];
     const float r2 = r * r;
@@ -504,8 +558,11 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float x)
 }
 
 // A work item is (walker, tile); each of the four wavefronts of a block takes
-// 64*J consecutive bins in J steps of 64 (lane l: bin s_j + l).  Per step the
-// wavefront evaluates all modes at its 64 bins.  For every mode it keeps, in
+// 64*J consecutive bins in J/NB steps of 64*NB (lane l: bins s_j + 64 b + l,
+// b < NB).  Per step the wavefront evaluates all modes at its bins; with
+// NB = 2 each coefficient fetch of the uniform path serves two bins per lane,
+// which halves the scalar loads and interval bookkeeping per bin and gives
+// every wavefront two independent evaluation chains.  For every mode it keeps, in
 // scalar registers, the sparse interval of its current step and the first
 // bin of the next interval (integer bin bounds from kbin).  A step inside one
 // interval (the common case: intervals span tens to tens of thousands of
@@ -517,15 +574,18 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float x)
 // kF32 selects the FP32 stage: whitened FP32 data, FP32 template, and
 // Kahan-compensated FP32 sums of <d|h> and <h|h> (the residual is formed in
 // the reduction from the FP64 <d|d>).
-template <bool kWriteH, bool kF32>
-__global__ __launch_bounds__(kDenseThreads, 4) void k_dense(DenseArgs a)
+template <bool kWriteH, bool kF32, int NB>
+__global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseArgs a)
 {
+    static_assert(NB == 1 || (!kWriteH && !kF32), "two bins per lane only on the FP64 likelihood path");
     __shared__ double red[kDenseThreads / 64][kPartials];
+    __shared__ double2 rot[kRotN];
     const int total = min(a.wbase[a.B], a.max_items);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ns = a.ns;
     CisConst K;
-    load_cis(K, a.cis_tab);
+    load_cis(K, a.cis_tab, rot);
+    __syncthreads();
     CisConst32 Kf;
     if (kF32) load_cis32(Kf, a.cis32);
     int item = blockIdx.x, end = total, step = gridDim.x;
@@ -579,35 +639,48 @@ __global__ __launch_bounds__(kDenseThreads, 4) void k_dense(DenseArgs a)
 #pragma unroll
         for (int q = 0; q < 6; ++q) ks[q] = kc[q] = 0.0f;
 
-        for (int j = 0; j < a.steps; ++j) {
+        // a step covers 64*NB bins; lane l takes bins s0 + 64 b + l
+        for (int j = 0; j < a.steps; j += NB) {
             const int s0 = kw + 64 * j;
-            const int k = s0 + lane;
-            const bool inw = (k >= wb.klo) && (k <= wb.khi);
-            const int idx = inw ? k - a.k0 : 0;
-            double2 dv[3];
-            double wv[3];
+            int k[NB], idx[NB];
+            bool inw[NB];
+            double f[NB];
+            double2 dv[NB][3];
+            double wv[NB][3];
             float2 dv32[3];
             float sv32[3];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                k[b] = s0 + 64 * b + lane;
+                inw[b] = (k[b] >= wb.klo) && (k[b] <= wb.khi);
+                idx[b] = inw[b] ? k[b] - a.k0 : 0;
+                f[b] = (double)k[b] * a.df;
+            }
             if (!kWriteH && !kF32) {
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    dv[ch] = a.d[(size_t)ch * a.n + idx];
-                    wv[ch] = a.w[(size_t)ch * a.n + idx];
-                }
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) {
+                        dv[b][ch] = a.d[(size_t)ch * a.n + idx[b]];
+                        wv[b][ch] = a.w[(size_t)ch * a.n + idx[b]];
+                    }
             }
             if (!kWriteH && kF32) {
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
-                    dv32[ch] = a.dw32[(size_t)ch * a.n + idx];
-                    sv32[ch] = a.sw32[(size_t)ch * a.n + idx];
+                    dv32[ch] = a.dw32[(size_t)ch * a.n + idx[0]];
+                    sv32[ch] = a.sw32[(size_t)ch * a.n + idx[0]];
                 }
             }
-            const double f = (double)k * a.df;
-            double hr[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+            double hr[NB][3], hi[NB][3];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) hr[b][ch] = hi[b][ch] = 0.0;
             float hr32[3] = {0.0f, 0.0f, 0.0f}, hi32[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int m = 0; m < kMaxModes; ++m) {
-                const int lo = max(s0, mlo[m]), hi_ = min(s0 + 63, mhi[m]);
+                const int lo = max(s0, mlo[m]), hi_ = min(s0 + 64 * NB - 1, mhi[m]);
                 if (lo > hi_) continue;
                 // knots and bin bounds of (walker, mode) start at kbo, its
                 // intervals at ivo = kbo - wm; one shared base pointer per
@@ -619,35 +692,46 @@ __global__ __launch_bounds__(kDenseThreads, 4) void k_dense(DenseArgs a)
                     cur[m] = uni_i(cur[m] + 1);
                     nxt[m] = uni_i(cur[m] < ns - 2 ? ((cint *)a.kbin)[kbo + cur[m] + 1] : 0x7fffffff);
                 }
-                const bool in = (k >= mlo[m]) && (k <= mhi[m]);
+                bool in[NB];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) in[b] = (k[b] >= mlo[m]) && (k[b] <= mhi[m]);
                 if (hi_ < nxt[m]) {
                     const int iv = cur[m];
                     const double x0 = ((cdouble *)a.kf)[kbo + iv];
                     const size_t c0 = (size_t)(ivo + iv) * kCoefPerIv;
-                    if (in) {
+                    if (NB > 1) {
+                        double dx[NB];
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) dx[b] = f[b] - x0;
+                        mode_bins_u<NB>(K, (cdouble *)a.coef + c0, dx, in, hr, hi);
+                    } else if (in[0]) {
                         if (kF32)
                             mode_bin32<cdouble *, cfloat *>(K, Kf, (cdouble *)a.coef + c0, (cfloat *)a.coef32 + c0,
-                                                            f - x0, hr32, hi32);
+                                                            f[0] - x0, hr32, hi32);
                         else
-                            mode_bin<cdouble *>(K, (cdouble *)a.coef + c0, f - x0, hr, hi);
+                            mode_bin<cdouble *>(K, (cdouble *)a.coef + c0, f[0] - x0, hr[0], hi[0]);
                     }
-                } else if (in) {
-                    int iv = cur[m];
-                    while (iv < ns - 2 && a.kbin[kbo + iv + 1] <= k) ++iv;
-                    const size_t c0 = (size_t)(ivo + iv) * kCoefPerIv;
-                    if (kF32)
-                        mode_bin32<const double *, const float *>(K, Kf, a.coef + c0, a.coef32 + c0,
-                                                                  f - a.kf[kbo + iv], hr32, hi32);
-                    else
-                        mode_bin<const double *>(K, a.coef + c0, f - a.kf[kbo + iv], hr, hi);
+                } else {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        if (!in[b]) continue;
+                        int iv = cur[m];
+                        while (iv < ns - 2 && a.kbin[kbo + iv + 1] <= k[b]) ++iv;
+                        const size_t c0 = (size_t)(ivo + iv) * kCoefPerIv;
+                        if (kF32)
+                            mode_bin32<const double *, const float *>(K, Kf, a.coef + c0, a.coef32 + c0,
+                                                                      f[0] - a.kf[kbo + iv], hr32, hi32);
+                        else
+                            mode_bin<const double *>(K, a.coef + c0, f[b] - a.kf[kbo + iv], hr[b], hi[b]);
+                    }
                 }
             }
             if (kWriteH) {
-                if (inw)
+                if (inw[0])
 #pragma unroll
-                    for (int ch = 0; ch < 3; ++ch) a.h[(size_t)ch * a.n + idx] = make_double2(hr[ch], hi[ch]);
+                    for (int ch = 0; ch < 3; ++ch) a.h[(size_t)ch * a.n + idx[0]] = make_double2(hr[0][ch], hi[0][ch]);
             } else if (kF32) {
-                if (inw) {
+                if (inw[0]) {
 #pragma unroll
                     for (int ch = 0; ch < 3; ++ch) {
                         // whitened template h sqrt(w); <d|h> and <h|h> are summed
@@ -660,13 +744,17 @@ __global__ __launch_bounds__(kDenseThreads, 4) void k_dense(DenseArgs a)
                         kahan_add(ks[3 + ch], kc[3 + ch], fmaf(wr, wr, wi * wi));
                     }
                 }
-            } else if (inw) {
+            } else {
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    const double rr = dv[ch].x - hr[ch], ri = dv[ch].y - hi[ch];
-                    acc[ch] = fma(fma(rr, rr, ri * ri), wv[ch], acc[ch]);
-                    acc[3 + ch] = fma(fma(dv[ch].x, hr[ch], dv[ch].y * hi[ch]), wv[ch], acc[3 + ch]);
-                    acc[6 + ch] = fma(fma(hr[ch], hr[ch], hi[ch] * hi[ch]), wv[ch], acc[6 + ch]);
+                for (int b = 0; b < NB; ++b) {
+                    if (!inw[b]) continue;
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) {
+                        const double rr = dv[b][ch].x - hr[b][ch], ri = dv[b][ch].y - hi[b][ch];
+                        acc[ch] = fma(fma(rr, rr, ri * ri), wv[b][ch], acc[ch]);
+                        acc[3 + ch] = fma(fma(dv[b][ch].x, hr[b][ch], dv[b][ch].y * hi[b][ch]), wv[b][ch], acc[3 + ch]);
+                        acc[6 + ch] = fma(fma(hr[b][ch], hr[b][ch], hi[b][ch] * hi[b][ch]), wv[b][ch], acc[6 + ch]);
+                    }
                 }
             }
         }
@@ -817,8 +905,23 @@ __global__ void k_coef32(const double *__restrict__ coef, float *__restrict__ co
 
 const double *cis_table_host(int *n)
 {
-    *n = kCisN;
-    return kCisHost;
+    // cos and sin of j pi/32 from long double, rounded once to double;
+    // built on first use (thread-safe static initialisation)
+    struct Tab {
+        double v[kCisN + 2 * kRotN];
+        Tab()
+        {
+            const long double pi = 3.141592653589793238462643383279502884L;
+            for (int i = 0; i < kCisN; ++i) v[i] = kCisHost[i];
+            for (int j = 0; j < kRotN; ++j) {
+                v[kCisN + 2 * j] = (double)cosl(pi * j / 32.0L);
+                v[kCisN + 2 * j + 1] = (double)sinl(pi * j / 32.0L);
+            }
+        }
+    };
+    static const Tab tab;
+    *n = kCisN + 2 * kRotN;
+    return tab.v;
 }
 
 const float *cis32_table_host(int *n)
@@ -876,9 +979,9 @@ hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &w
     hipError_t e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     if (g.precision == 0)
-        k_dense<false, false><<<grid, kDenseThreads, 0, st>>>(a);
+        k_dense<false, false, kBinsPerLane><<<grid, kDenseThreads, 0, st>>>(a);
     else
-        k_dense<false, true><<<grid, kDenseThreads, 0, st>>>(a);
+        k_dense<false, true, 1><<<grid, kDenseThreads, 0, st>>>(a);
     if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -908,7 +1011,7 @@ hipError_t launch_template(const Modes &md, const GridDesc &g, const Work &wk, d
     launch_items(1, g, wk, max_items, st);
     DenseArgs a = make_args(1, md, g, wk, none, max_items);
     a.h = h;
-    k_dense<true, false><<<dense_grid(1, Schedule()), kDenseThreads, 0, st>>>(a);
+    k_dense<true, false, 1><<<dense_grid(1, Schedule()), kDenseThreads, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -26,6 +26,9 @@ constexpr int kCoefPerIv = kNumFn * 4;  // 32 doubles per sparse interval
 constexpr int kDenseThreads = 256;
 constexpr int kMaxDenseSteps = 32;
 constexpr int kMinDenseSteps = 4;
+constexpr int kBinsPerLane = 2;   // bins per lane per step of the FP64 dense kernel
+static_assert(kMinDenseSteps % kBinsPerLane == 0, "steps per wavefront must be a multiple of the bins per lane");
+constexpr int kCisTabDoubles = 256;   // device table of the dense-stage sin/cos constants
 constexpr int kPartials = 9;       // R_c, DH_c, HH_c for c = A, E, T
 
 // Per-walker constants of the waveform model (built by the source kernel).

@@ -92,6 +92,18 @@ def integrated_time(chain: np.ndarray, c_window: float = 5.0) -> float:
     return float(taus[M])
 
 
+def batch_means_se(chain: np.ndarray, n_batches: int = 20) -> np.ndarray:
+    """Standard error of the ensemble mean of chain[N, W, D] per parameter,
+    from the spread of the means of n_batches consecutive blocks of steps.
+    Unlike the walker-averaged autocorrelation it also sees correlation
+    between walkers (an ensemble that drifts or mixes slowly as a whole)."""
+    x = np.asarray(chain, dtype=np.float64)
+    nb = max(2, min(n_batches, x.shape[0]))
+    per = x.shape[0] // nb
+    means = x[: nb * per].reshape(nb, per, *x.shape[1:]).mean(axis=(1, 2))   # [nb][D]
+    return means.std(axis=0, ddof=1) / math.sqrt(nb)
+
+
 def ess(chain: np.ndarray, c_window: float = 5.0):
     """Effective sample size of chain[N, W, D]: N W / max_d tau_d.
     Returns (ess, tau_max, taus)."""
@@ -502,7 +514,7 @@ def _arm_report(smp: PTSampler, chain: np.ndarray, wall: float, burn: int):
 
 def ess_comparison(loglike: Callable, logprior: Callable, x0: np.ndarray, betas, seconds: float,
                    burn_seconds: float, seeds=(5, 55), a: float = 1.15, p_flow: float = 0.8,
-                   max_train: int = 200000, flow_kwargs=None, fit_kwargs=None, log=None):
+                   max_train: int = 200000, flow_kwargs=None, fit_kwargs=None, log=None, keep_chains=False):
     """Stretch-move PT against stretch + flow PT on the same target.
 
     One stretch-only burn-in of burn_seconds from x0[T][W][D] is shared and
@@ -514,7 +526,11 @@ def ess_comparison(loglike: Callable, logprior: Callable, x0: np.ndarray, betas,
     'seconds', the flow arm's training included.  ESS (Sec. III.C) counts
     the arm's T = 1 chain; ESS/s divides by the arm's wall time.  Accuracy:
     per-parameter means of the two arms agree within 3 combined Monte Carlo
-    standard errors, and standard deviations within 5 %.
+    standard errors, and standard deviations within 5 %.  Also reported: the
+    mean differences in batch-means standard errors (which see correlation
+    between walkers) and the stretch arm's first half against its second half
+    (a drift check).  keep_chains adds both arms' T = 1 chains to the result
+    under 'chains'.
     """
     say = log or (lambda *_: None)
     dim = x0.shape[-1]
@@ -560,11 +576,22 @@ def ess_comparison(loglike: Callable, logprior: Callable, x0: np.ndarray, betas,
     a1, a2 = ch_plain.reshape(-1, dim), ch_flow.reshape(-1, dim)
     e1, e2 = max(out["stretch"]["ess"], 1.0), max(out["stretch_flow"]["ess"], 1.0)
     se = np.sqrt(a1.var(0) / e1 + a2.var(0) / e2)
+    se_bm = np.sqrt(batch_means_se(ch_plain) ** 2 + batch_means_se(ch_flow) ** 2)
+    h = len(ch_plain) // 2
+    se_drift = np.sqrt(batch_means_se(ch_plain[:h], 10) ** 2 + batch_means_se(ch_plain[h:], 10) ** 2)
     with np.errstate(divide="ignore", invalid="ignore"):
-        zmax = float(np.nanmax(np.abs(a1.mean(0) - a2.mean(0)) / se))
+        z = np.abs(a1.mean(0) - a2.mean(0)) / se
+        z_bm = np.abs(a1.mean(0) - a2.mean(0)) / se_bm
+        z_drift = np.abs(ch_plain[:h].reshape(-1, dim).mean(0) - ch_plain[h:].reshape(-1, dim).mean(0)) / se_drift
+        zmax = float(np.nanmax(z))
         sd_rel = float(np.nanmax(np.abs(a2.std(0) / a1.std(0) - 1)))
     out["accuracy"] = {"max_mean_diff_in_se": round(zmax, 3), "max_sd_rel_diff": round(sd_rel, 4),
-                       "equal": bool(zmax < 3 and sd_rel < 0.05)}
+                       "equal": bool(zmax < 3 and sd_rel < 0.05),
+                       "mean_diff_in_se": [round(float(v), 2) for v in z],
+                       "mean_diff_in_batch_means_se": [round(float(v), 2) for v in z_bm],
+                       "stretch_arm_half_vs_half_in_batch_means_se": [round(float(v), 2) for v in z_drift]}
+    if keep_chains:
+        out["chains"] = (ch_plain, ch_flow)
     out["ess_per_s_gain"] = round(out["stretch_flow"]["ess_per_s"] / max(out["stretch"]["ess_per_s"], 1e-12), 3)
     prop.flow.close()
     return out

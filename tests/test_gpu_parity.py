@@ -134,7 +134,7 @@ def test_schedules_give_identical_bits(small):
         assert L.get_schedule() == (bpc, one)
         assert np.array_equal(L.loglike(w.walkers).cpu().numpy(), ref)
     best, ms = L.autotune(w.walkers, reps=3)
-    assert best in (2, 4, 6, 8, 12, 16) and ms > 0
+    assert best in (2, 3, 4, 6, 8, 9, 12, 16, 24, 32) and ms > 0
     assert L.get_schedule() == (best, False)
     assert np.array_equal(L.loglike(w.walkers).cpu().numpy(), ref)
     L.set_schedule(8, False)

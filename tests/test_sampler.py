@@ -51,6 +51,35 @@ def _gauss_target(dim, seed):
     return mu, cov, ll
 
 
+def test_batch_means_standard_error():
+    """AR(1) walkers: the standard error of the ensemble mean is
+    sqrt(tau / (N W)) per unit variance; walkers that share a common slow
+    component (here one AR(1) path added to every walker) are correlated with
+    each other, which the batch means see and the walker-averaged
+    autocorrelation (own-mean per walker) does not."""
+    rng = np.random.default_rng(7)
+    r, n, w = 0.8, 20000, 32
+    e = rng.standard_normal((n, w, 3))
+    x = np.empty_like(e)
+    x[0] = e[0]
+    for t in range(1, n):
+        x[t] = r * x[t - 1] + math.sqrt(1 - r * r) * e[t]
+    se = S.batch_means_se(x, 40)
+    want = math.sqrt((1 + r) / (1 - r) / (n * w))
+    assert np.all(np.abs(se / want - 1) < 0.35), se / want
+    # a shared slow drift: same AR(1) path (r = 0.999) in every walker
+    c = np.empty(n)
+    c[0] = 0.0
+    g = rng.standard_normal(n)
+    for t in range(1, n):
+        c[t] = 0.999 * c[t - 1] + math.sqrt(1 - 0.999 ** 2) * g[t]
+    y = x + 0.3 * c[:, None, None]
+    se_y = S.batch_means_se(y, 40)
+    _, tau_y, _ = S.ess(y)
+    naive = np.sqrt(y.reshape(-1, 3).var(0) * tau_y / (n * w))
+    assert np.all(se_y > 3 * naive)
+
+
 def test_stretch_move_recovers_correlated_gaussian():
     dim = 11
     mu, cov, ll = _gauss_target(dim, 3)
