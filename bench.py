@@ -32,7 +32,7 @@ FP64_PEAK_TFLOPS = 78.6            # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 
 FLOPS_PER_MODE_BIN = 111           # 8 cubics 48, e^{i phi} 37, A e^{i phi} 2, 3 complex MACs 24
 FLOPS_PER_WALKER_BIN = 51          # per channel: d-h 2, |r|^2 w 5, Re(d h*) w 5, |h|^2 w 5
 BYTES_PER_WALKER_BIN = 72          # d (3 x complex128) + w (3 x float64), streamed per walker
-KERNEL_REV = "dense-v14"           # traffic counters are only reused for this kernel revision
+KERNEL_REV = "dense-v15"           # traffic counters are only reused for this kernel revision
 
 
 def parse():
@@ -128,7 +128,8 @@ def sampler_comparison(args):
     torch.cuda.synchronize()
     result = {"metric": "ESS/s at T = 1, stretch + learned proposal vs stretch only", "unit": "ESS/s",
               "value": rep["stretch_flow"]["ess_per_s"], "baseline_value": rep["stretch"]["ess_per_s"],
-              "gain": rep["ess_per_s_gain"], "higher_is_better": True, "n_gpus": 1, "dtype": "f64",
+              "gain": rep["ess_per_s_gain"], "gain_batch_means": rep["ess_per_s_gain_batch_means"],
+              "higher_is_better": True, "n_gpus": 1, "dtype": "f64",
               "data": "synthetic (seeded injection + Gaussian noise, analytic PSD)",
               "config": {"workload": w.name, "rungs": nt, "walkers_per_rung": nw, "stretch_a": 1.15,
                          "burn_in_seconds": args.sampler_burn, "seconds_per_arm": args.sampler, "seeds": [5, 55]},
@@ -208,9 +209,30 @@ def precision_study(args):
         h = L0.template(inj).cpu().numpy()
         data = h + inputs.noise(g, psd, w.noise_seed)
         res = {}
+        speed = {}
         for name, prec in (("fp64", mbh.MBH_FP64), ("fp32c", mbh.MBH_FP32C)):
             L = mbh.Likelihood(g, data, psd, w.modes, w.ns, w.t0, precision=prec, max_batch=B)
             res[name] = L.loglike(walkers).cpu().numpy()
+            if not cases:
+                # speed of each path on this batch (autotuned launch shape; the
+                # dense kernel timed with HIP events, the whole step by the host)
+                p_dev = torch.as_tensor(walkers, dtype=torch.float64, device="cuda")
+                out = torch.empty(B, dtype=torch.float64, device="cuda")
+                bpc, _ = L.autotune(p_dev, reps=3)
+                L.loglike(p_dev, out=out)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(5):
+                    L.loglike(p_dev, out=out)
+                torch.cuda.synchronize()
+                step_ms = (time.perf_counter() - t0) * 1e3 / 5
+                L.set_timing(True)
+                for _ in range(5):
+                    L.loglike(p_dev, out=out)
+                dms, cnt = L.get_timing()
+                L.set_timing(False)
+                speed[name] = {"dense_ms": round(dms / max(cnt, 1), 3), "ms_per_step": round(step_ms, 3),
+                               "evals_per_s": round(B / (step_ms * 1e-3), 1), "dense_workgroups_per_cu": bpc}
             L.close()
         d = np.abs(res["fp32c"] - res["fp64"])
         bound = 5e-9 * snr * snr + 1e-6 * snr + 1e-5
@@ -220,6 +242,8 @@ def precision_study(args):
                                           "p99": float(np.quantile(d, 0.99))},
                 "max_err_over_bound": float((d / bound).max()),
                 "log10_abs_err_histogram": {"edges": [int(e) for e in edges], "counts": [int(c) for c in hist]}}
+        if speed:
+            case["speed"] = speed
         if not args.no_cpu_baseline:
             from oracle import oracle as O
             O.build()

@@ -221,6 +221,7 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
     TRY(dalloc(c, &c->wk.item_w, (size_t)c->max_items));
     TRY(dalloc(c, &c->wk.item_t, (size_t)c->max_items));
     TRY(dalloc(c, &c->wk.tile_off, (size_t)ntile_max + 1));
+    TRY(dalloc(c, &c->wk.ticket, (size_t)64));
     TRY(dalloc(c, &c->wk.wbase, (size_t)B + 1));
     TRY(dalloc(c, &c->wk.partial, (size_t)c->max_items * kPartials));
     TRY(dalloc(c, &c->wk.out7, (size_t)B * 7));

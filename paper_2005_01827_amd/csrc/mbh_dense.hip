@@ -204,8 +204,10 @@ __global__ __launch_bounds__(256) void k_tile_count(int B, const WalkerBand *__r
 }
 
 // exclusive scan of the per-tile counts in place (single workgroup of 1024)
-__global__ __launch_bounds__(1024) void k_tile_scan(int ntiles, int *__restrict__ tile_off)
+__global__ __launch_bounds__(1024) void k_tile_scan(int ntiles, int *__restrict__ tile_off, int *__restrict__ ticket)
 {
+    // the dense kernel that follows takes its items from this counter
+    if (threadIdx.x == 0) ticket[0] = 0;
     __shared__ int sh[1024];
     int carry = 0;
     for (int b0 = 0; b0 < ntiles; b0 += 1024) {
@@ -266,6 +268,8 @@ struct DenseArgs {
     double df;
     int max_items;
     int one_per_walker;
+    int use_ticket;      // take items from *ticket instead of a fixed stride
+    int *ticket;
     const ModeBand *band;
     const WalkerBand *wband;
     const int *wbase;
@@ -588,13 +592,27 @@ __global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseA
     __syncthreads();
     CisConst32 Kf;
     if (kF32) load_cis32(Kf, a.cis32);
+    // Items: a fixed stride over the tile-major list, the items of one walker
+    // (one_per_walker), or the next free item from a counter (tickets): a
+    // workgroup that finishes early takes more, and workgroups running
+    // together stay on neighbouring items of the list.  The next ticket is
+    // requested when an item starts and published at its last barrier.
+    __shared__ int next_item;
+    const bool tickets = !kWriteH && a.use_ticket && !a.one_per_walker;
     int item = blockIdx.x, end = total, step = gridDim.x;
     if (a.one_per_walker) {
         item = a.wbase[blockIdx.x];
         end = min(a.wbase[blockIdx.x + 1], total);
         step = 1;
     }
-    for (; item < end; item += step) {
+    if (tickets) {
+        if (threadIdx.x == 0) next_item = atomicAdd(a.ticket, 1);
+        __syncthreads();
+        item = uni_i(next_item);
+    }
+    while (item < end) {
+        int ticket_next = 0;
+        if (tickets && threadIdx.x == 0) ticket_next = atomicAdd(a.ticket, 1);
         const int wk = a.one_per_walker ? (int)blockIdx.x : uni_i(a.item_w[item]);
         const WalkerBand wb = a.wband[wk];
         const int tile = a.one_per_walker ? wb.tile_lo + (item - a.wbase[wk]) : uni_i(a.item_t[item]);
@@ -758,7 +776,10 @@ __global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseA
                 }
             }
         }
-        if (kWriteH) continue;
+        if (kWriteH) {
+            item += step;
+            continue;
+        }
         if (kF32) {
 #pragma unroll
             for (int q = 0; q < 6; ++q) acc[3 + q] = (double)ks[q] - (double)kc[q];
@@ -782,7 +803,9 @@ __global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseA
             for (int wv = 0; wv < kDenseThreads / 64; ++wv) s += red[wv][threadIdx.x];
             a.partial[(size_t)slot * kPartials + threadIdx.x] = s;
         }
+        if (tickets && threadIdx.x == 0) next_item = ticket_next;
         __syncthreads();
+        item = tickets ? uni_i(next_item) : item + step;
     }
 }
 
@@ -855,6 +878,8 @@ DenseArgs make_args(int B, const Modes &md, const GridDesc &g, const Work &wk, c
     a.df = g.df;
     a.max_items = max_items;
     a.one_per_walker = 0;
+    a.use_ticket = 0;
+    a.ticket = wk.ticket;
     a.band = wk.band;
     a.wband = wk.wband;
     a.wbase = wk.wbase;
@@ -964,7 +989,7 @@ void launch_items(int B, const GridDesc &g, const Work &wk, int max_items, hipSt
 {
     const int ntiles = (g.n + g.tile_bins - 1) / g.tile_bins;
     k_tile_count<<<ntiles, 256, 0, st>>>(B, wk.wband, wk.tile_off);
-    k_tile_scan<<<1, 1024, 0, st>>>(ntiles, wk.tile_off);
+    k_tile_scan<<<1, 1024, 0, st>>>(ntiles, wk.tile_off, wk.ticket);
     k_tile_fill<<<ntiles, 256, 0, st>>>(B, wk.wband, wk.tile_off, wk.item_w, wk.item_t, max_items);
 }
 
@@ -975,6 +1000,7 @@ hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &w
     launch_items(B, g, wk, max_items, st);
     DenseArgs a = make_args(B, md, g, wk, dt, max_items);
     a.one_per_walker = sch.one_per_walker;
+    a.use_ticket = sch.one_per_walker ? 0 : 1;
     const int grid = dense_grid(B, sch);
     hipError_t e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;

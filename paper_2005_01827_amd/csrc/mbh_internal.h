@@ -101,6 +101,7 @@ struct Work {
     int *item_w;            // [max items] walker of each work item (tile-major order)
     int *item_t;            // [max items] tile of each work item
     int *tile_off;          // [tiles + 1] first item of each tile
+    int *ticket;            // next work item of the dense kernel (zeroed by the tile scan)
     int *wbase;             // [B+1]  exclusive scan of ntiles; wbase[B] = total
     double *partial;        // [max items][9]
     double *out7;           // [B][7] default output
