@@ -119,7 +119,9 @@ mbh_status mbh_template(mbh_ctx *ctx, const double *params_dev, double *h_dev, v
  * any pointer may be NULL.  band_host[nm][4] = {active, klo, khi, 0};
  * fband_host[nm][2] = {f_start, f_end}; f_host[nm][ns] knots;
  * fn_host[nm][8][ns] = A, phi, Re/Im T^A, Re/Im T^E, Re/Im T^T;
- * coef_host[nm][8][ns-1][4].  Synchronous on 'stream'. */
+ * coef_host[nm][8][ns-1][4], the cubic of interval i in powers of f - f_i
+ * (c0 + c1 (f - f_i) + c2 (f - f_i)^2 + c3 (f - f_i)^3).  Synchronous on
+ * 'stream'. */
 mbh_status mbh_get_sparse(mbh_ctx *ctx, int w, int64_t *band_host, double *fband_host, double *f_host,
                           double *fn_host, double *coef_host, void *stream);
 

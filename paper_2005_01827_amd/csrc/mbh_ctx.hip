@@ -517,17 +517,30 @@ mbh_status mbh_get_sparse(mbh_ctx *ctx, int w, int64_t *band_host, double *fband
                                   hipMemcpyDeviceToHost)) != hipSuccess)
         return hip_fail(ctx, e, "copy values");
     if (coef_host) {
-        // device layout [nm][ns-1][8][4] -> host layout [nm][8][ns-1][4]
-        std::vector<double> tmp((size_t)nm * (ns - 1) * kCoefPerIv);
+        // device layout [nm][ns-1][8][4], each cubic centred on the first dense
+        // bin of the next interval (fc = kbin[i+1] df); host layout
+        // [nm][8][ns-1][4] in powers of f - f_i: a Taylor shift by f_i - fc
+        std::vector<double> tmp((size_t)nm * (ns - 1) * kCoefPerIv), kf((size_t)nm * ns);
+        std::vector<int> kb((size_t)nm * ns);
         if ((e = hipMemcpy(tmp.data(), ctx->wk.coef + (size_t)w * nm * (ns - 1) * kCoefPerIv, sizeof(double) * tmp.size(),
+                           hipMemcpyDeviceToHost)) != hipSuccess ||
+            (e = hipMemcpy(kf.data(), ctx->wk.kf + (size_t)w * nm * ns, sizeof(double) * kf.size(),
+                           hipMemcpyDeviceToHost)) != hipSuccess ||
+            (e = hipMemcpy(kb.data(), ctx->wk.kbin + (size_t)w * nm * ns, sizeof(int) * kb.size(),
                            hipMemcpyDeviceToHost)) != hipSuccess)
             return hip_fail(ctx, e, "copy coefficients");
         for (int im = 0; im < nm; ++im)
-            for (int i = 0; i < ns - 1; ++i)
-                for (int q = 0; q < kNumFn; ++q)
-                    for (int c = 0; c < 4; ++c)
-                        coef_host[(((size_t)im * kNumFn + q) * (ns - 1) + i) * 4 + c] =
-                            tmp[(((size_t)im * (ns - 1) + i) * kNumFn + q) * 4 + c];
+            for (int i = 0; i < ns - 1; ++i) {
+                const double sh = kf[(size_t)im * ns + i] - (double)kb[(size_t)im * ns + i + 1] * ctx->g.df;
+                for (int q = 0; q < kNumFn; ++q) {
+                    const double *c = &tmp[(((size_t)im * (ns - 1) + i) * kNumFn + q) * 4];
+                    double *o = &coef_host[(((size_t)im * kNumFn + q) * (ns - 1) + i) * 4];
+                    o[0] = c[0] + sh * (c[1] + sh * (c[2] + sh * c[3]));
+                    o[1] = c[1] + sh * (2.0 * c[2] + 3.0 * sh * c[3]);
+                    o[2] = c[2] + 3.0 * sh * c[3];
+                    o[3] = c[3];
+                }
+            }
     }
     return MBH_OK;
 }

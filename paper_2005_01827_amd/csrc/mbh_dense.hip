@@ -645,7 +645,7 @@ __global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseA
                     mlo[m] = uni_i(mb.klo);
                     mhi[m] = uni_i(mb.khi);
                     cur[m] = i;
-                    nxt[m] = uni_i(i < ns - 2 ? kb[i + 1] : 0x7fffffff);
+                    nxt[m] = uni_i(kb[i + 1]);
                 }
             }
         }
@@ -706,16 +706,18 @@ __global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseA
                 const int wm = wk * a.nm + m;
                 const int kbo = uni_i(wm * ns);
                 const int ivo = kbo - wm;
-                while (nxt[m] <= lo) {
+                while (cur[m] < ns - 2 && nxt[m] <= lo) {
                     cur[m] = uni_i(cur[m] + 1);
-                    nxt[m] = uni_i(cur[m] < ns - 2 ? ((cint *)a.kbin)[kbo + cur[m] + 1] : 0x7fffffff);
+                    nxt[m] = uni_i(((cint *)a.kbin)[kbo + cur[m] + 1]);
                 }
                 bool in[NB];
 #pragma unroll
                 for (int b = 0; b < NB; ++b) in[b] = (k[b] >= mlo[m]) && (k[b] <= mhi[m]);
                 if (hi_ < nxt[m]) {
+                    // the cubics of interval i are centred on the first bin of
+                    // the next interval, kbin[i+1] = nxt: no knot load needed
                     const int iv = cur[m];
-                    const double x0 = ((cdouble *)a.kf)[kbo + iv];
+                    const double x0 = (double)nxt[m] * a.df;
                     const size_t c0 = (size_t)(ivo + iv) * kCoefPerIv;
                     if (NB > 1) {
                         double dx[NB];
@@ -736,11 +738,12 @@ __global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseA
                         int iv = cur[m];
                         while (iv < ns - 2 && a.kbin[kbo + iv + 1] <= k[b]) ++iv;
                         const size_t c0 = (size_t)(ivo + iv) * kCoefPerIv;
+                        const double xc = (double)a.kbin[kbo + iv + 1] * a.df;
                         if (kF32)
                             mode_bin32<const double *, const float *>(K, Kf, a.coef + c0, a.coef32 + c0,
-                                                                      f[0] - a.kf[kbo + iv], hr32, hi32);
+                                                                      f[0] - xc, hr32, hi32);
                         else
-                            mode_bin<const double *>(K, a.coef + c0, f[b] - a.kf[kbo + iv], hr[b], hi[b]);
+                            mode_bin<const double *>(K, a.coef + c0, f[b] - xc, hr[b], hi[b]);
                     }
                 }
             }

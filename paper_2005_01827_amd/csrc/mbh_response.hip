@@ -159,6 +159,16 @@ __global__ void k_response(int B, Modes md, GridDesc g, const Source *__restrict
 // f_i <= k df < f_{i+1} in double precision.
 constexpr int kSplineU = 16;
 
+// First dense bin k with k df >= x (|x/df| < 2^31): the ceiling of the
+// rounded quotient is within one of it, so one correction each way is exact.
+__device__ __forceinline__ int first_bin(double x, double df)
+{
+    long long k = (long long)ceil(x / df);
+    if ((double)k * df < x) ++k;
+    if ((double)(k - 1) * df >= x) --k;
+    return (int)max(-1LL, min(k, 0x7ffffffeLL));
+}
+
 __global__ void k_spline(int B, Modes md, GridDesc g, const ModeBand *__restrict__ band,
                          const double *__restrict__ kf, const double *__restrict__ fn, double *__restrict__ coef,
                          double *__restrict__ scratch, int *__restrict__ kbin)
@@ -182,17 +192,7 @@ __global__ void k_spline(int B, Modes md, GridDesc g, const ModeBand *__restrict
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int i = i0 + u * kNumFn;
-                if (i < ns) {
-                    // ceil of the rounded quotient is within one of the first k
-                    // with k df >= f (|f/df| < 2^31, quotient error < 1e-6), so one
-                    // correction each way makes it exact
-                    long long k = act ? (long long)ceil(xs[u] / g.df) : 0;
-                    if (act) {
-                        if ((double)k * g.df < xs[u]) ++k;
-                        if ((double)(k - 1) * g.df >= xs[u]) --k;
-                    }
-                    kb[i] = (int)max(-1LL, min(k, 0x7ffffffeLL));
-                }
+                if (i < ns) kb[i] = act ? first_bin(xs[u], g.df) : 0;
             }
         }
     }
@@ -270,7 +270,10 @@ __global__ void k_spline(int B, Modes md, GridDesc g, const ModeBand *__restrict
         const double ha = x[ns - 2] - x[ns - 3], hb = x[ns - 1] - x[ns - 2];
         Mv[(size_t)(ns - 1) * nt] = ((ha + hb) * Mv[(size_t)(ns - 2) * nt] - hb * Mv[(size_t)(ns - 3) * nt]) / ha;
     }
-    // coefficients of interval i from knots i, i+1
+    // coefficients of interval i from knots i, i+1, then re-centred on
+    // fc = kbin[i+1] df, the first dense bin of the next interval: the dense
+    // stage evaluates q(f - fc) = p(f - x_i) with q(t) = p(t + fc - x_i), and
+    // takes fc from the interval bound it already holds
     double x0 = x[0], y0 = y[0], m0 = Mv[0];
     for (int i0 = 0; i0 < ns - 1; i0 += U) {
         double xs[U], ys[U], ms[U];
@@ -288,11 +291,13 @@ __global__ void k_spline(int B, Modes md, GridDesc g, const ModeBand *__restrict
             const double x1 = xs[u], y1 = ys[u], m1 = ms[u];
             const double h = x1 - x0;
             const double sl = (y1 - y0) / h;
+            const double p0 = y0, p1 = sl - h * (2.0 * m0 + m1) / 6.0, p2 = 0.5 * m0, p3 = (m1 - m0) / (6.0 * h);
+            const double dl = (double)first_bin(x1, g.df) * g.df - x0;
             double *o = out + (size_t)i * kCoefPerIv;
-            o[0] = y0;
-            o[1] = sl - h * (2.0 * m0 + m1) / 6.0;
-            o[2] = 0.5 * m0;
-            o[3] = (m1 - m0) / (6.0 * h);
+            o[0] = fma(fma(fma(p3, dl, p2), dl, p1), dl, p0);
+            o[1] = fma(fma(3.0 * p3, dl, 2.0 * p2), dl, p1);
+            o[2] = fma(3.0 * p3, dl, p2);
+            o[3] = p3;
             x0 = x1; y0 = y1; m0 = m1;
         }
     }
