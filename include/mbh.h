@@ -107,7 +107,10 @@ mbh_status mbh_response(mbh_ctx *ctx, int B, void *stream);
 mbh_status mbh_interp_and_inner(mbh_ctx *ctx, int B, double *out7_dev, void *stream);
 
 /* The three stages above in one call, launched as one captured HIP graph per
- * (B, stream) after the first call: logL_dev[B] (device) receives ln L. */
+ * (B, stream) after the first call: logL_dev[B] (device) receives ln L.  On
+ * the FP64 path the dense stage accumulates only the residual sums here (ln L
+ * needs nothing else), so ln L is bitwise the value mbh_interp_and_inner
+ * returns. */
 mbh_status mbh_loglike_batch(mbh_ctx *ctx, const double *params_dev, int B, double *logL_dev, void *stream);
 
 /* Dense template of one walker on the context's grid, h_dev[3][n][2]

@@ -131,7 +131,7 @@ mbh_status enqueue_all(mbh_ctx *c, const double *params, int B, double *out7, do
     if ((e = launch_spline(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "spline");
     if ((e = launch_coef32(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "coef32");
     if ((e = launch_walker_bands(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "bands");
-    if ((e = launch_dense(B, c->md, c->g, c->wk, data_of(c), c->max_items, c->sch, st, ev0, ev1)) != hipSuccess)
+    if ((e = launch_dense(B, c->md, c->g, c->wk, data_of(c), c->max_items, c->sch, false, st, ev0, ev1)) != hipSuccess)
         return hip_fail(c, e, "dense");
     if ((e = launch_reduce(B, c->g, c->wk, data_of(c), out7, logL, st)) != hipSuccess) return hip_fail(c, e, "reduce");
     return MBH_OK;
@@ -303,7 +303,7 @@ mbh_status mbh_interp_and_inner(mbh_ctx *ctx, int B, double *out7_dev, void *str
     if (B > 0 && !out7_dev) return fail(ctx, MBH_EINVAL, "mbh: null out7");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_walker_bands(B, ctx->md, ctx->g, ctx->wk, s);
-    if (e == hipSuccess) e = launch_dense(B, ctx->md, ctx->g, ctx->wk, data_of(ctx), ctx->max_items, ctx->sch, s);
+    if (e == hipSuccess) e = launch_dense(B, ctx->md, ctx->g, ctx->wk, data_of(ctx), ctx->max_items, ctx->sch, true, s);
     if (e == hipSuccess) e = launch_reduce(B, ctx->g, ctx->wk, data_of(ctx), out7_dev, nullptr, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "interp_and_inner");
     return MBH_OK;
@@ -444,7 +444,7 @@ mbh_status mbh_autotune(mbh_ctx *ctx, const double *params_dev, int B, int reps,
         sch.blocks_per_cu = c;
         std::vector<float> ms;
         for (int r = 0; r < reps && e == hipSuccess; ++r) {
-            e = launch_dense(B, ctx->md, ctx->g, ctx->wk, data_of(ctx), ctx->max_items, sch, s, e0, e1);
+            e = launch_dense(B, ctx->md, ctx->g, ctx->wk, data_of(ctx), ctx->max_items, sch, false, s, e0, e1);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float t = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);

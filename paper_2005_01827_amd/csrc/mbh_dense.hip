@@ -578,10 +578,13 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float x)
 // kF32 selects the FP32 stage: whitened FP32 data, FP32 template, and
 // Kahan-compensated FP32 sums of <d|h> and <h|h> (the residual is formed in
 // the reduction from the FP64 <d|d>).
-template <bool kWriteH, bool kF32, int NB>
+// kROnly: accumulate only the residual sums R_c (ln L needs nothing else on
+// the FP64 path); <d|h>_c and <h|h>_c are then left at zero.
+template <bool kWriteH, bool kF32, int NB, bool kROnly>
 __global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseArgs a)
 {
     static_assert(NB == 1 || (!kWriteH && !kF32), "two bins per lane only on the FP64 likelihood path");
+    static_assert(!kROnly || (!kWriteH && !kF32), "residual-only sums only on the FP64 likelihood path");
     __shared__ double red[kDenseThreads / 64][kPartials];
     __shared__ double2 rot[kRotN];
     const int total = min(a.wbase[a.B], a.max_items);
@@ -773,8 +776,11 @@ __global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseA
                     for (int ch = 0; ch < 3; ++ch) {
                         const double rr = dv[b][ch].x - hr[b][ch], ri = dv[b][ch].y - hi[b][ch];
                         acc[ch] = fma(fma(rr, rr, ri * ri), wv[b][ch], acc[ch]);
-                        acc[3 + ch] = fma(fma(dv[b][ch].x, hr[b][ch], dv[b][ch].y * hi[b][ch]), wv[b][ch], acc[3 + ch]);
-                        acc[6 + ch] = fma(fma(hr[b][ch], hr[b][ch], hi[b][ch] * hi[b][ch]), wv[b][ch], acc[6 + ch]);
+                        if (!kROnly) {
+                            acc[3 + ch] =
+                                fma(fma(dv[b][ch].x, hr[b][ch], dv[b][ch].y * hi[b][ch]), wv[b][ch], acc[3 + ch]);
+                            acc[6 + ch] = fma(fma(hr[b][ch], hr[b][ch], hi[b][ch] * hi[b][ch]), wv[b][ch], acc[6 + ch]);
+                        }
                     }
                 }
             }
@@ -997,7 +1003,7 @@ void launch_items(int B, const GridDesc &g, const Work &wk, int max_items, hipSt
 }
 
 hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &wk, const Data &dt, int max_items,
-                        const Schedule &sch, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
+                        const Schedule &sch, bool inner, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (B <= 0) return hipSuccess;
     launch_items(B, g, wk, max_items, st);
@@ -1007,10 +1013,12 @@ hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &w
     const int grid = dense_grid(B, sch);
     hipError_t e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
-    if (g.precision == 0)
-        k_dense<false, false, kBinsPerLane><<<grid, kDenseThreads, 0, st>>>(a);
+    if (g.precision != 0)
+        k_dense<false, true, 1, false><<<grid, kDenseThreads, 0, st>>>(a);
+    else if (inner)
+        k_dense<false, false, kBinsPerLane, false><<<grid, kDenseThreads, 0, st>>>(a);
     else
-        k_dense<false, true, 1><<<grid, kDenseThreads, 0, st>>>(a);
+        k_dense<false, false, kBinsPerLane, true><<<grid, kDenseThreads, 0, st>>>(a);
     if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -1040,7 +1048,7 @@ hipError_t launch_template(const Modes &md, const GridDesc &g, const Work &wk, d
     launch_items(1, g, wk, max_items, st);
     DenseArgs a = make_args(1, md, g, wk, none, max_items);
     a.h = h;
-    k_dense<true, false, 1><<<dense_grid(1, Schedule()), kDenseThreads, 0, st>>>(a);
+    k_dense<true, false, 1, false><<<dense_grid(1, Schedule()), kDenseThreads, 0, st>>>(a);
     return hipGetLastError();
 }
 

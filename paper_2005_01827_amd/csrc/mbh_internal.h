@@ -152,9 +152,11 @@ struct Schedule {
 
 int num_cus();
 
-// ev0/ev1 (optional) are recorded on st right before and after the dense kernel.
+// ev0/ev1 (optional) are recorded on st right before and after the dense
+// kernel.  inner = false: the FP64 path accumulates only the residual sums
+// (enough for ln L); <d|h>_c and <h|h>_c of the output are then zero.
 hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &wk, const Data &dt,
-                        int max_items, const Schedule &sch, hipStream_t st, hipEvent_t ev0 = nullptr,
+                        int max_items, const Schedule &sch, bool inner, hipStream_t st, hipEvent_t ev0 = nullptr,
                         hipEvent_t ev1 = nullptr);
 
 hipError_t launch_reduce(int B, const GridDesc &g, const Work &wk, const Data &dt, double *out7,
