@@ -292,28 +292,29 @@ struct DenseArgs {
 
 __device__ __forceinline__ int uni_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// e^{i phi} = e^{i q pi/32} e^{i r}.  t = phi 32/pi is rounded to the
+// e^{i phi} = e^{i q pi/128} e^{i r}.  t = phi 128/pi is rounded to the
 // integer q by adding and subtracting 1.5 2^52 (exact for |t| < 2^51), which
-// leaves q mod 2^32 in the low word of the sum; r = phi - q pi/32 with a
-// two-part pi/32 (two FMAs), so |r| <= pi/64 up to rounding.  On that range
-// the Taylor polynomials of sin r (to r^7) and cos r (to r^8) truncate below
-// 5e-18, and e^{i q pi/32} is entry q mod 64 of a table of cos and sin of
-// j pi/32, staged in LDS: one per-lane LDS read replaces the quadrant logic
+// leaves q mod 2^32 in the low word of the sum; r = phi - q pi/128 with a
+// two-part pi/128 (two FMAs), so |r| <= pi/256 up to rounding.  On that range
+// the Taylor polynomials of sin r (to r^5) and cos r (to r^6) truncate below
+// 1e-17, and e^{i q pi/128} is entry q mod 256 of a table of cos and sin of
+// j pi/128, staged in LDS: one per-lane LDS read replaces the quadrant logic
 // and most of the polynomial of a reduction modulo pi/2.
 //
 // Device table layout (filled once per context): kCisN constants, then the
 // kRotN (cos, sin) pairs.
-constexpr int kRotN = 64;
-constexpr int kCisN = 12;
-constexpr int kTwoOverPi = 10;   // 2/pi, for the quarter-turn reduction of the FP32 stage
+constexpr int kRotN = 256;
+constexpr int kCisN = 8;
+constexpr int kCisPoly = 6;      // constants used by cis(): 128/pi, pi/128 (two parts), sin and cos terms
+constexpr int kTwoOverPi = 6;    // 2/pi, for the quarter-turn reduction of the FP32 stage
 constexpr double kRoundShift = 6755399441055744.0;   // 1.5 * 2^52
 static_assert(kCisN % 2 == 0 && kCisN + 2 * kRotN <= kCisTabDoubles, "rotation table must fit the device table");
 const double kCisHost[kCisN] = {
-    10.185916357881301489,                                    // 32/pi
-    3.141592653589793116 / 32.0,                              // pi/32 rounded to double (exact scaling of pi)
-    1.2246467991473532e-16 / 32.0,                            // pi/32 - the above
-    -1.0 / 5040.0, 1.0 / 120.0, -1.0 / 6.0,                   // sin: r^7 .. r^3
-    1.0 / 40320.0, -1.0 / 720.0, 1.0 / 24.0, -0.5,            // cos: r^8 .. r^2
+    40.743665431525205956,                                    // 128/pi
+    3.141592653589793116 / 128.0,                             // pi/128 rounded to double (exact scaling of pi)
+    1.2246467991473532e-16 / 128.0,                           // pi/128 - the above
+    1.0 / 120.0, -1.0 / 6.0,                                  // sin: r^5, r^3
+    -1.0 / 720.0,                                             // cos: r^6 (r^4 and r^2 are 1/24 and -1/2)
     0.63661977236758134308,                                   // 2/pi
     0.0};
 
@@ -321,7 +322,7 @@ typedef const __attribute__((address_space(4))) double cdouble;
 typedef const __attribute__((address_space(4))) int cint;
 
 struct CisConst {
-    double k[kTwoOverPi];
+    double k[kCisPoly];
     double two_over_pi;
     const double2 *rot;   // kRotN entries in LDS
 };
@@ -344,7 +345,7 @@ __device__ __forceinline__ void load_cis(CisConst &K, const double *tab, double2
 {
     const double *t = tab + lane_zero();
 #pragma unroll
-    for (int i = 0; i < kTwoOverPi; ++i) K.k[i] = t[i];
+    for (int i = 0; i < kCisPoly; ++i) K.k[i] = t[i];
     K.two_over_pi = t[kTwoOverPi];
     for (int i = threadIdx.x; i < kRotN; i += blockDim.x)
         rot_lds[i] = ((const double2 *)(tab + kCisN))[i];
@@ -359,12 +360,10 @@ __device__ __forceinline__ void cis(const CisConst &K, double phi, double &sn, d
     double r = fma(-q, K.k[1], phi);
     r = fma(-q, K.k[2], r);
     const double r2 = r * r;
-    double ps = fma(K.k[3], r2, K.k[4]);
-    ps = fma(ps, r2, K.k[5]);
+    const double ps = fma(K.k[3], r2, K.k[4]);
     const double sr = fma(r * r2, ps, r);
-    double pc = fma(K.k[6], r2, K.k[7]);
-    pc = fma(pc, r2, K.k[8]);
-    pc = fma(pc, r2, K.k[9]);
+    double pc = fma(K.k[5], r2, 1.0 / 24.0);
+    pc = fma(pc, r2, -0.5);
     const double cr = fma(r2, pc, 1.0);
     cs = fma(e.x, cr, -(e.y * sr));
     sn = fma(e.y, cr, e.x * sr);
@@ -552,6 +551,35 @@ __device__ __forceinline__ void mode_bin32(const CisConst &K, const CisConst32 &
     }
 }
 
+// FP32 stage, NB bins of a lane in one interval (see mode_bins_u).
+template <int NB>
+__device__ __forceinline__ void mode_bins32_u(const CisConst &K, const CisConst32 &Kf, cdouble *cd, cfloat *cf,
+                                              const double (&dx)[NB], const bool (&in)[NB], float (&hr)[NB][3],
+                                              float (&hi)[NB][3])
+{
+    float ar[NB], ai[NB], dxf[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const double ph = cubic_s(cd + 4, dx[b]);
+        dxf[b] = (float)dx[b];
+        const float amp = in[b] ? cubic32_s(cf + 0, dxf[b]) : 0.0f;
+        float sn, cs;
+        cis32(K, Kf, ph, sn, cs);
+        ar[b] = amp * cs;
+        ai[b] = amp * sn;
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const float tr = cubic32_s(cf + 8 + 8 * ch, dxf[b]);
+            const float ti = cubic32_s(cf + 12 + 8 * ch, dxf[b]);
+            hr[b][ch] = fmaf(tr, ar[b], fmaf(-ti, ai[b], hr[b][ch]));
+            hi[b][ch] = fmaf(tr, ai[b], fmaf(ti, ar[b], hi[b][ch]));
+        }
+}
+
 // Kahan-compensated FP32 sum: s + c carries the running total.
 __device__ __forceinline__ void kahan_add(float &s, float &c, float x)
 {
@@ -581,9 +609,9 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float x)
 // kROnly: accumulate only the residual sums R_c (ln L needs nothing else on
 // the FP64 path); <d|h>_c and <h|h>_c are then left at zero.
 template <bool kWriteH, bool kF32, int NB, bool kROnly>
-__global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseArgs a)
+__global__ __launch_bounds__(kDenseThreads, (NB == 1 || kF32) ? 4 : 3) void k_dense(DenseArgs a)
 {
-    static_assert(NB == 1 || (!kWriteH && !kF32), "two bins per lane only on the FP64 likelihood path");
+    static_assert(NB == 1 || !kWriteH, "two bins per lane only on the likelihood paths");
     static_assert(!kROnly || (!kWriteH && !kF32), "residual-only sums only on the FP64 likelihood path");
     __shared__ double red[kDenseThreads / 64][kPartials];
     __shared__ double2 rot[kRotN];
@@ -668,8 +696,8 @@ __global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseA
             double f[NB];
             double2 dv[NB][3];
             double wv[NB][3];
-            float2 dv32[3];
-            float sv32[3];
+            float2 dv32[NB][3];
+            float sv32[NB][3];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 k[b] = s0 + 64 * b + lane;
@@ -688,17 +716,23 @@ __global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseA
             }
             if (!kWriteH && kF32) {
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    dv32[ch] = a.dw32[(size_t)ch * a.n + idx[0]];
-                    sv32[ch] = a.sw32[(size_t)ch * a.n + idx[0]];
-                }
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) {
+                        dv32[b][ch] = a.dw32[(size_t)ch * a.n + idx[b]];
+                        sv32[b][ch] = a.sw32[(size_t)ch * a.n + idx[b]];
+                    }
             }
             double hr[NB][3], hi[NB][3];
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) hr[b][ch] = hi[b][ch] = 0.0;
-            float hr32[3] = {0.0f, 0.0f, 0.0f}, hi32[3] = {0.0f, 0.0f, 0.0f};
+            float hr32[NB][3], hi32[NB][3];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) hr32[b][ch] = hi32[b][ch] = 0.0f;
 #pragma unroll
             for (int m = 0; m < kMaxModes; ++m) {
                 const int lo = max(s0, mlo[m]), hi_ = min(s0 + 64 * NB - 1, mhi[m]);
@@ -726,11 +760,15 @@ __global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseA
                         double dx[NB];
 #pragma unroll
                         for (int b = 0; b < NB; ++b) dx[b] = f[b] - x0;
-                        mode_bins_u<NB>(K, (cdouble *)a.coef + c0, dx, in, hr, hi);
+                        if (kF32)
+                            mode_bins32_u<NB>(K, Kf, (cdouble *)a.coef + c0, (cfloat *)a.coef32 + c0, dx, in, hr32,
+                                              hi32);
+                        else
+                            mode_bins_u<NB>(K, (cdouble *)a.coef + c0, dx, in, hr, hi);
                     } else if (in[0]) {
                         if (kF32)
                             mode_bin32<cdouble *, cfloat *>(K, Kf, (cdouble *)a.coef + c0, (cfloat *)a.coef32 + c0,
-                                                            f[0] - x0, hr32, hi32);
+                                                            f[0] - x0, hr32[0], hi32[0]);
                         else
                             mode_bin<cdouble *>(K, (cdouble *)a.coef + c0, f[0] - x0, hr[0], hi[0]);
                     }
@@ -744,7 +782,7 @@ __global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseA
                         const double xc = (double)a.kbin[kbo + iv + 1] * a.df;
                         if (kF32)
                             mode_bin32<const double *, const float *>(K, Kf, a.coef + c0, a.coef32 + c0,
-                                                                      f[0] - xc, hr32, hi32);
+                                                                      f[b] - xc, hr32[b], hi32[b]);
                         else
                             mode_bin<const double *>(K, a.coef + c0, f[b] - xc, hr[b], hi[b]);
                     }
@@ -755,7 +793,9 @@ __global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseA
 #pragma unroll
                     for (int ch = 0; ch < 3; ++ch) a.h[(size_t)ch * a.n + idx[0]] = make_double2(hr[0][ch], hi[0][ch]);
             } else if (kF32) {
-                if (inw[0]) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (!inw[b]) continue;
 #pragma unroll
                     for (int ch = 0; ch < 3; ++ch) {
                         // whitened template h sqrt(w); <d|h> and <h|h> are summed
@@ -763,8 +803,8 @@ __global__ __launch_bounds__(kDenseThreads, NB == 1 ? 4 : 3) void k_dense(DenseA
                         // the FP64 <d|d> (summing the residual directly in FP32
                         // was measured to be less accurate: the FP32 whitened
                         // data then add an error floor of ~1e-4 per walker)
-                        const float wr = hr32[ch] * sv32[ch], wi = hi32[ch] * sv32[ch];
-                        kahan_add(ks[ch], kc[ch], fmaf(dv32[ch].x, wr, dv32[ch].y * wi));
+                        const float wr = hr32[b][ch] * sv32[b][ch], wi = hi32[b][ch] * sv32[b][ch];
+                        kahan_add(ks[ch], kc[ch], fmaf(dv32[b][ch].x, wr, dv32[b][ch].y * wi));
                         kahan_add(ks[3 + ch], kc[3 + ch], fmaf(wr, wr, wi * wi));
                     }
                 }
@@ -939,7 +979,7 @@ __global__ void k_coef32(const double *__restrict__ coef, float *__restrict__ co
 
 const double *cis_table_host(int *n)
 {
-    // cos and sin of j pi/32 from long double, rounded once to double;
+    // cos and sin of j pi/128 from long double, rounded once to double;
     // built on first use (thread-safe static initialisation)
     struct Tab {
         double v[kCisN + 2 * kRotN];
@@ -948,8 +988,8 @@ const double *cis_table_host(int *n)
             const long double pi = 3.141592653589793238462643383279502884L;
             for (int i = 0; i < kCisN; ++i) v[i] = kCisHost[i];
             for (int j = 0; j < kRotN; ++j) {
-                v[kCisN + 2 * j] = (double)cosl(pi * j / 32.0L);
-                v[kCisN + 2 * j + 1] = (double)sinl(pi * j / 32.0L);
+                v[kCisN + 2 * j] = (double)cosl(pi * j / (kRotN / 2));
+                v[kCisN + 2 * j + 1] = (double)sinl(pi * j / (kRotN / 2));
             }
         }
     };
@@ -1014,7 +1054,7 @@ hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &w
     hipError_t e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     if (g.precision != 0)
-        k_dense<false, true, 1, false><<<grid, kDenseThreads, 0, st>>>(a);
+        k_dense<false, true, kBinsPerLane, false><<<grid, kDenseThreads, 0, st>>>(a);
     else if (inner)
         k_dense<false, false, kBinsPerLane, false><<<grid, kDenseThreads, 0, st>>>(a);
     else
