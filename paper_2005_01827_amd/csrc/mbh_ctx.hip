@@ -216,7 +216,6 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
     TRY(dalloc(c, &c->wk.kt, (size_t)B * nm * ns));
     TRY(dalloc(c, &c->wk.fn, (size_t)B * nm * kNumFn * ns));
     TRY(dalloc(c, &c->wk.coef, (size_t)B * nm * (ns - 1) * kCoefPerIv));
-    TRY(dalloc(c, &c->wk.spline_scratch, (size_t)B * nm * kNumFn * 2 * ns));
     TRY(dalloc(c, &c->wk.kbin, (size_t)B * nm * ns));
     TRY(dalloc(c, &c->wk.item_w, (size_t)c->max_items));
     TRY(dalloc(c, &c->wk.item_t, (size_t)c->max_items));

@@ -96,7 +96,6 @@ struct Work {
     double *kt;             // [B][nm][ns]        t_lm at the knots
     double *fn;             // [B][nm][8][ns]     function values at the knots
     double *coef;           // [B][nm][ns-1][8][4] spline coefficients
-    double *spline_scratch; // [B][nm][8][2 ns]
     int *kbin;              // [B][nm][ns] first dense bin k with k df >= knot
     int *item_w;            // [max items] walker of each work item (tile-major order)
     int *item_t;            // [max items] tile of each work item

@@ -43,7 +43,7 @@ __device__ inline Cplx cscale(Cplx a, double s) { return {a.re * s, a.im * s}; }
 __device__ inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
 // One thread per (walker, mode, knot): T^{A,E,T} and the total phase.
-__global__ void k_response(int B, Modes md, GridDesc g, const Source *__restrict__ src,
+__global__ __launch_bounds__(128) void k_response(int B, Modes md, GridDesc g, const Source *__restrict__ src,
                            const ModeBand *__restrict__ band, const double *__restrict__ kf,
                            const double *__restrict__ kt, double *__restrict__ fn)
 {
@@ -144,21 +144,6 @@ __global__ void k_response(int B, Modes md, GridDesc g, const Source *__restrict
     fnm[7 * ns + j] = TT.im;
 }
 
-// One thread per (walker, mode, function): not-a-knot spline through
-// (f_j, y_j).  Unknowns M_1..M_{ns-2} (second derivatives); M_0 and M_{ns-1}
-// follow from continuity of the third derivative at f_1 and f_{ns-2}.
-// The Thomas sweep keeps 2*ns doubles per thread in scratch, interleaved
-// across threads (element r of thread id at r*nt + id) so that the 64 lanes
-// of a wavefront touch consecutive addresses.  Each of the three serial
-// sweeps loads kSplineU knots' operands at once and then runs kSplineU steps
-// from registers, so a step waits on memory once per kSplineU steps rather
-// than once per step.  The kNumFn threads of each (walker, mode) also write
-// kbin[i] for i = q mod kNumFn: the first dense bin k with k df >= f_i, so
-// that the dense stage can find intervals by integer comparison: bin k lies
-// in interval i iff kbin[i] <= k < kbin[i+1], which is the same as
-// f_i <= k df < f_{i+1} in double precision.
-constexpr int kSplineU = 16;
-
 // First dense bin k with k df >= x (|x/df| < 2^31): the ceiling of the
 // rounded quotient is within one of it, so one correction each way is exact.
 __device__ __forceinline__ int first_bin(double x, double df)
@@ -169,63 +154,62 @@ __device__ __forceinline__ int first_bin(double x, double df)
     return (int)max(-1LL, min(k, 0x7ffffffeLL));
 }
 
-__global__ void k_spline(int B, Modes md, GridDesc g, const ModeBand *__restrict__ band,
-                         const double *__restrict__ kf, const double *__restrict__ fn, double *__restrict__ coef,
-                         double *__restrict__ scratch, int *__restrict__ kbin)
+constexpr int kSplineThreads = 256;
+constexpr int kSplineRows = 4;     // rows per thread: ns - 2 <= 1024
+
+// Functions solved together: all eight while their right-hand sides fit in
+// LDS beside the matrix, else four at a time.
+__host__ __device__ inline int spline_group(int ns) { return ns <= 512 ? kNumFn : kNumFn / 2; }
+inline size_t spline_lds_bytes(int ns)
 {
-    constexpr int U = kSplineU;
-    const int ns = g.ns;
-    const int nt = B * md.nm * kNumFn;
-    const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nt) return;
-    const int q = id % kNumFn;
-    const int wm = id / kNumFn;
-    double *out = coef + (size_t)wm * (ns - 1) * kCoefPerIv + q * 4;
+    const int m = ns - 2, G = spline_group(ns);
+    return sizeof(double) * ((size_t)(3 + G) * m + 2 * G);
+}
+
+// Not-a-knot splines through (f_j, y_j), one workgroup per (walker, mode).
+// Unknowns M_1..M_{ns-2} (second derivatives; row r <-> M_{r+1}); M_0 and
+// M_{ns-1} follow from continuity of the third derivative at f_1 and
+// f_{ns-2}.  The matrix depends only on the knots, so the eight functions of
+// a mode share it; it is strictly diagonally dominant (also the two modified
+// end rows), so parallel cyclic reduction is stable: in round k every row
+// eliminates its neighbours at distance 2^k, and after ceil(log2(ns-2))
+// rounds each row stands alone, M = d / b.  The workgroup also writes
+// kbin[i], the first dense bin k with k df >= f_i, so that the dense stage
+// finds intervals by integer comparison (bin k lies in interval i iff
+// kbin[i] <= k < kbin[i+1], the same as f_i <= k df < f_{i+1}), and stores
+// the cubic of interval i re-centred on fc = kbin[i+1] df, the first dense
+// bin of the next interval: q(t) = p(t + fc - f_i), evaluated by the dense
+// stage at t = f - fc.
+template <int G>
+__global__ __launch_bounds__(kSplineThreads) void k_spline(int B, Modes md, GridDesc g,
+                                                           const ModeBand *__restrict__ band,
+                                                           const double *__restrict__ kf,
+                                                           const double *__restrict__ fn,
+                                                           double *__restrict__ coef, int *__restrict__ kbin)
+{
+    extern __shared__ double sm[];
+    const int ns = g.ns, m = ns - 2;
+    const int wm = blockIdx.x;
+    if (wm >= B * md.nm) return;
     const double *x = kf + (size_t)wm * ns;
+    double *out = coef + (size_t)wm * (ns - 1) * kCoefPerIv;
     const bool act = band[wm].active != 0;
     {
         int *kb = kbin + (size_t)wm * ns;
-        for (int i0 = q; i0 < ns; i0 += U * kNumFn) {
-            double xs[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) xs[u] = x[min(i0 + u * kNumFn, ns - 1)];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * kNumFn;
-                if (i < ns) kb[i] = act ? first_bin(xs[u], g.df) : 0;
-            }
-        }
+        for (int i = threadIdx.x; i < ns; i += kSplineThreads) kb[i] = act ? first_bin(x[i], g.df) : 0;
     }
     if (!act) {
-        for (int i = 0; i < ns - 1; ++i)
-            for (int c = 0; c < 4; ++c) out[(size_t)i * kCoefPerIv + c] = 0.0;
+        for (int i = threadIdx.x; i < (ns - 1) * kCoefPerIv; i += kSplineThreads) out[i] = 0.0;
         return;
     }
-    const double *y = fn + ((size_t)wm * kNumFn + q) * ns;
-    double *cp = scratch + id;                    // cp[r]  -> cp[r * nt]
-    double *Mv = scratch + (size_t)ns * nt + id;  // Mv[i]  -> Mv[i * nt]
-    const int m = ns - 2;  // unknowns M_1..M_{ns-2}, row r <-> M_{r+1}
-
-    // forward elimination; row r uses knots r, r+1, r+2
-    double prev_c = 0.0, prev_d = 0.0;
-    double xa = x[0], xb = x[1], ya = y[0], yb = y[1];
-    for (int r0 = 0; r0 < m; r0 += U) {
-        double xs[U], ys[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = min(r0 + u + 2, ns - 1);
-            xs[u] = x[j];
-            ys[u] = y[j];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = r0 + u;
-            if (r >= m) continue;
-            const double xc = xs[u], yc = ys[u];
-            const double h0 = xb - xa, h1 = xc - xb;
-            const double s0 = (yb - ya) / h0, s1 = (yc - yb) / h1;
+    double *A = sm, *Bm = sm + m, *C = sm + 2 * m, *D = sm + 3 * m;   // D[G][m]
+    double *M0 = D + (size_t)G * m, *M1 = M0 + G;                       // M_0, M_{ns-1} per function
+    for (int q0 = 0; q0 < kNumFn; q0 += G) {
+        // the system: matrix rows and right-hand sides 6 (s_{i} - s_{i-1})
+        for (int r = threadIdx.x; r < m; r += kSplineThreads) {
+            const int i = r + 1;
+            const double h0 = x[i] - x[i - 1], h1 = x[i + 1] - x[i];
             double sub = h0, dia = 2.0 * (h0 + h1), sup = h1;
-            const double rhs = 6.0 * (s1 - s0);
             if (r == 0) {
                 dia = (h0 + h1) * (h0 + 2.0 * h1) / h1;
                 sup = (h1 * h1 - h0 * h0) / h1;
@@ -236,70 +220,77 @@ __global__ void k_spline(int B, Modes md, GridDesc g, const ModeBand *__restrict
                 sub = (h0 * h0 - h1 * h1) / h0;
                 sup = 0.0;
             }
-            const double den = dia - sub * prev_c;
-            const double c = sup / den;
-            const double d = (rhs - sub * prev_d) / den;
-            cp[(size_t)r * nt] = c;
-            Mv[(size_t)(r + 1) * nt] = d;   // holds d_r until back substitution
-            prev_c = c;
-            prev_d = d;
-            xa = xb; xb = xc; ya = yb; yb = yc;
+            A[r] = sub;
+            Bm[r] = dia;
+            C[r] = sup;
+            for (int q = 0; q < G; ++q) {
+                const double *y = fn + ((size_t)wm * kNumFn + q0 + q) * ns;
+                D[(size_t)q * m + r] = 6.0 * ((y[i + 1] - y[i]) / h1 - (y[i] - y[i - 1]) / h0);
+            }
         }
-    }
-    // back substitution: M_{m} = d_{m-1}; M_{r+1} = d_r - c_r M_{r+2} for r = m-2 .. 0
-    double mn = prev_d;
-    for (int r0 = m - 2; r0 >= 0; r0 -= U) {
-        double ds[U], cs[U];
+        __syncthreads();
+        // cyclic reduction rounds
+        for (int s = 1; s < m; s *= 2) {
+            double na[kSplineRows], nb[kSplineRows], nc[kSplineRows], nd[kSplineRows][G];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = max(r0 - u, 0);
-            ds[u] = Mv[(size_t)(r + 1) * nt];
-            cs[u] = cp[(size_t)r * nt];
+            for (int u = 0; u < kSplineRows; ++u) {
+                const int r = threadIdx.x + u * kSplineThreads;
+                if (r >= m) continue;
+                const bool lo = r - s >= 0, hi = r + s < m;
+                const double al = lo ? -A[r] / Bm[r - s] : 0.0;
+                const double ga = hi ? -C[r] / Bm[r + s] : 0.0;
+                na[u] = lo ? al * A[r - s] : 0.0;
+                nc[u] = hi ? ga * C[r + s] : 0.0;
+                nb[u] = Bm[r] + (lo ? al * C[r - s] : 0.0) + (hi ? ga * A[r + s] : 0.0);
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    const double *dq = D + (size_t)q * m;
+                    nd[u][q] = dq[r] + (lo ? al * dq[r - s] : 0.0) + (hi ? ga * dq[r + s] : 0.0);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kSplineRows; ++u) {
+                const int r = threadIdx.x + u * kSplineThreads;
+                if (r >= m) continue;
+                A[r] = na[u];
+                Bm[r] = nb[u];
+                C[r] = nc[u];
+#pragma unroll
+                for (int q = 0; q < G; ++q) D[(size_t)q * m + r] = nd[u][q];
+            }
+            __syncthreads();
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = r0 - u;
-            if (r < 0) continue;
-            mn = ds[u] - cs[u] * mn;
-            Mv[(size_t)(r + 1) * nt] = mn;
+        // M_{r+1} = d_r / b_r, in place
+        for (int t = threadIdx.x; t < G * m; t += kSplineThreads) D[t] /= Bm[t % m];
+        __syncthreads();
+        // end values from the not-a-knot conditions
+        if (threadIdx.x < G) {
+            const double *Mq = D + (size_t)threadIdx.x * m;   // Mq[r] = M_{r+1}
+            const double h0 = x[1] - x[0], h1 = x[2] - x[1];
+            M0[threadIdx.x] = ((h0 + h1) * Mq[0] - h0 * Mq[1]) / h1;
+            const double ha = x[ns - 2] - x[ns - 3], hb = x[ns - 1] - x[ns - 2];
+            M1[threadIdx.x] = ((ha + hb) * Mq[m - 1] - hb * Mq[m - 2]) / ha;
         }
-    }
-    {
-        const double h0 = x[1] - x[0], h1 = x[2] - x[1];
-        Mv[0] = ((h0 + h1) * Mv[(size_t)nt] - h0 * Mv[(size_t)2 * nt]) / h1;
-        const double ha = x[ns - 2] - x[ns - 3], hb = x[ns - 1] - x[ns - 2];
-        Mv[(size_t)(ns - 1) * nt] = ((ha + hb) * Mv[(size_t)(ns - 2) * nt] - hb * Mv[(size_t)(ns - 3) * nt]) / ha;
-    }
-    // coefficients of interval i from knots i, i+1, then re-centred on
-    // fc = kbin[i+1] df, the first dense bin of the next interval: the dense
-    // stage evaluates q(f - fc) = p(f - x_i) with q(t) = p(t + fc - x_i), and
-    // takes fc from the interval bound it already holds
-    double x0 = x[0], y0 = y[0], m0 = Mv[0];
-    for (int i0 = 0; i0 < ns - 1; i0 += U) {
-        double xs[U], ys[U], ms[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = min(i0 + u + 1, ns - 1);
-            xs[u] = x[j];
-            ys[u] = y[j];
-            ms[u] = Mv[(size_t)j * nt];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u;
-            if (i >= ns - 1) continue;
-            const double x1 = xs[u], y1 = ys[u], m1 = ms[u];
-            const double h = x1 - x0;
-            const double sl = (y1 - y0) / h;
-            const double p0 = y0, p1 = sl - h * (2.0 * m0 + m1) / 6.0, p2 = 0.5 * m0, p3 = (m1 - m0) / (6.0 * h);
-            const double dl = (double)first_bin(x1, g.df) * g.df - x0;
-            double *o = out + (size_t)i * kCoefPerIv;
+        __syncthreads();
+        // coefficients of interval i from knots i, i+1, re-centred on fc
+        for (int t = threadIdx.x; t < (ns - 1) * G; t += kSplineThreads) {
+            const int i = t / G, q = t % G;
+            const double *Mq = D + (size_t)q * m;
+            const double *y = fn + ((size_t)wm * kNumFn + q0 + q) * ns;
+            const double mi = i == 0 ? M0[q] : Mq[i - 1];
+            const double mj = i + 1 == ns - 1 ? M1[q] : Mq[i];
+            const double x0 = x[i], h = x[i + 1] - x0;
+            const double sl = (y[i + 1] - y[i]) / h;
+            const double p0 = y[i], p1 = sl - h * (2.0 * mi + mj) / 6.0, p2 = 0.5 * mi, p3 = (mj - mi) / (6.0 * h);
+            const double dl = (double)first_bin(x[i + 1], g.df) * g.df - x0;
+            double *o = out + (size_t)i * kCoefPerIv + (q0 + q) * 4;
             o[0] = fma(fma(fma(p3, dl, p2), dl, p1), dl, p0);
             o[1] = fma(fma(3.0 * p3, dl, 2.0 * p2), dl, p1);
             o[2] = fma(3.0 * p3, dl, p2);
             o[3] = p3;
-            x0 = x1; y0 = y1; m0 = m1;
         }
+        __syncthreads();
     }
 }
 
@@ -316,8 +307,12 @@ hipError_t launch_response(int B, const Modes &md, const GridDesc &g, const Work
 hipError_t launch_spline(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st)
 {
     if (B <= 0) return hipSuccess;
-    const int nt = B * md.nm * kNumFn;
-    k_spline<<<(nt + 63) / 64, 64, 0, st>>>(B, md, g, wk.band, wk.kf, wk.fn, wk.coef, wk.spline_scratch, wk.kbin);
+    if (spline_group(g.ns) == kNumFn)
+        k_spline<kNumFn><<<B * md.nm, kSplineThreads, spline_lds_bytes(g.ns), st>>>(B, md, g, wk.band, wk.kf, wk.fn,
+                                                                                   wk.coef, wk.kbin);
+    else
+        k_spline<kNumFn / 2><<<B * md.nm, kSplineThreads, spline_lds_bytes(g.ns), st>>>(B, md, g, wk.band, wk.kf,
+                                                                                       wk.fn, wk.coef, wk.kbin);
     return hipGetLastError();
 }
 

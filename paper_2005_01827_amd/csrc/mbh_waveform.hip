@@ -139,7 +139,7 @@ __device__ double mode_time(const Source &s, int l, int m, double f)
 // ---------------------------------------------------------------------------
 // Kernel 1: per-walker constants (one thread per walker).
 // ---------------------------------------------------------------------------
-__global__ void k_source(const double *__restrict__ params, int B, double t0, Source *__restrict__ out)
+__global__ __launch_bounds__(128) void k_source(const double *__restrict__ params, int B, double t0, Source *__restrict__ out)
 {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= B) return;
@@ -246,7 +246,7 @@ __device__ void swsh_m2(int l, int m, double th, double ph, double &re, double &
 // (walker, mode).  f_start is the root of t_lm(f) = 0 by bisection to
 // adjacent doubles; f_end = min(band end, (m/2) 0.2 / M).
 // ---------------------------------------------------------------------------
-__global__ void k_bands(int B, Modes md, GridDesc g, const Source *__restrict__ src, ModeBand *__restrict__ band)
+__global__ __launch_bounds__(64) void k_bands(int B, Modes md, GridDesc g, const Source *__restrict__ src, ModeBand *__restrict__ band)
 {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= B * md.nm) return;
