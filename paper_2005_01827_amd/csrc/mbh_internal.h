@@ -25,7 +25,7 @@ constexpr int kCoefPerIv = kNumFn * 4;  // 32 doubles per sparse interval
 // its grid and batch size (dense_steps()).
 constexpr int kDenseThreads = 256;
 constexpr int kMaxDenseSteps = 32;
-constexpr int kMinDenseSteps = 4;
+constexpr int kMinDenseSteps = 2;
 constexpr int kBinsPerLane = 2;   // bins per lane per step of the FP64 dense kernel
 static_assert(kMinDenseSteps % kBinsPerLane == 0, "steps per wavefront must be a multiple of the bins per lane");
 constexpr int kCisTabDoubles = 1024;  // device table of the dense-stage sin/cos constants and rotations
