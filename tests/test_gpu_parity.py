@@ -254,6 +254,42 @@ def test_config3_uneven_sampled(oracle):
     _full_case(oracle, inputs.config3(2048), 16, 2002, 2048)
 
 
+def test_largest_batch_small_grid(oracle):
+    """The largest batch a context accepts, 65536 walkers (about 35 GB of
+    device workspace): every ln L finite and sampled walkers, first and last
+    included, against the oracle."""
+    import torch
+    from paper_2005_01827_amd import mbh
+    print("case: small grid, max_batch = 65536 walkers, 8 checked", flush=True)
+    w = inputs.small_config(8, seed=7)
+    g = w.grid
+    psd = inputs.psd_aet(g.freqs)
+    d = oracle.template(w.injection, g, w.modes, w.ns, w.t0) + inputs.noise(g, psd, 79)
+    walkers = inputs.ball(w.injection, 1 << 16, 1e-3, 31)
+    L = mbh.Likelihood(g, d, psd, w.modes, w.ns, w.t0, max_batch=1 << 16)
+    try:
+        got = L.loglike(walkers).cpu().numpy()
+        torch.cuda.synchronize()
+        idx = np.linspace(0, len(walkers) - 1, 8).astype(int)
+        ref = oracle.loglike(walkers[idx], g, d, psd, w.modes, w.ns, w.t0)
+        _report("max-batch-65536", got[idx], ref[:, 0])
+        assert np.all(_lnl_close(got[idx], ref[:, 0]))
+        assert np.all(np.isfinite(got))
+    finally:
+        L.close()
+
+
+@pytest.mark.slow
+def test_largest_knot_count_full_grid(oracle):
+    """1024 knots per mode for all six modes on the T_obs = 2^25 s grid: the
+    spline solve takes its four-functions-at-a-time path, and the dense stage
+    sees the shortest intervals at full size."""
+    import dataclasses
+    print("case: T_obs=2^25 grid, ns = 1024, 6 modes, 16 walkers, 3 checked", flush=True)
+    w = dataclasses.replace(inputs.config2(16), ns=1024)
+    _full_case(oracle, w, 3, 2003, 16)
+
+
 # ---------------------------------------------------------------------------
 # FP32 dense stage (FP64 phase and <d|d>, FP32 template, compensated FP32
 # sums of <d|h> and <h|h>).  ln L = -(<d|d> + <h|h> - 2<d|h>)/2 carries the
