@@ -147,9 +147,10 @@ mbh_status mbh_get_timing(mbh_ctx *ctx, double *dense_ms_total, int64_t *count);
 
 /* Launch shape of the dense interpolation + inner-product kernel (the
  * batching over sources of Sec. II.A).  blocks_per_cu (1..32) workgroups per
- * compute unit run a grid-stride loop over (walker, 2048-bin tile) work
- * items; with one_per_walker != 0 each walker's tiles go to one workgroup
- * instead (an unbalanced reference schedule for load-balance measurements).
+ * compute unit take (walker, tile) work items from a counter (a tile is 512
+ * to 8192 bins, chosen per context); with one_per_walker != 0 each walker's
+ * tiles go to one workgroup instead (an unbalanced reference schedule for
+ * load-balance measurements).
  * ln L is bitwise identical under every shape.  Drops the context's captured
  * graphs.  Synchronous.  Default: 8 blocks per CU, tiled. */
 mbh_status mbh_set_schedule(mbh_ctx *ctx, int blocks_per_cu, int one_per_walker);

@@ -8,8 +8,9 @@
 //
 // Work decomposition: the dense grid is cut into tiles of tile_bins bins;
 // work items (walker, tile) cover each walker's union band and are listed
-// tile-major (all walkers of tile 0, then tile 1, ...) for a grid-stride
-// loop, so that workgroups running together share a few data tiles in L2.
+// tile-major (all walkers of tile 0, then tile 1, ...); workgroups take the
+// next item from a counter, so that workgroups running together share a few
+// data tiles in L2 and the batch ends evenly.
 // Each item writes its 9 partial sums to a walker-major slot, and one
 // wavefront per walker adds its slots in a fixed order, so results do not
 // depend on the order or the launch shape (no floating-point atomics).

@@ -141,9 +141,9 @@ hipError_t launch_spline(int B, const Modes &md, const GridDesc &g, const Work &
 hipError_t launch_walker_bands(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st);
 
 // Launch shape of the dense kernel: blocks_per_cu workgroups per compute unit
-// in a grid-stride loop over the (walker, tile) items, or, with
-// one_per_walker, one workgroup per walker walking its own tiles (the
-// unbalanced reference schedule).
+// taking (walker, tile) items from a counter, or, with one_per_walker, one
+// workgroup per walker walking its own tiles (the unbalanced reference
+// schedule).
 struct Schedule {
     int blocks_per_cu = 8;
     int one_per_walker = 0;

@@ -16,7 +16,7 @@
 //
 // Spline setup (Sec. II.A): not-a-knot cubic splines of the eight real
 // functions of each mode (A, phi, Re/Im T^A, T^E, T^T) over the log-spaced
-// knots, by a Thomas solve of the second-derivative system.
+// knots, by parallel cyclic reduction of the second-derivative system.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
