@@ -535,7 +535,8 @@ def ess_comparison(loglike: Callable, logprior: Callable, x0: np.ndarray, betas,
     'seconds', the flow arm's training included.  ESS (Sec. III.C) counts
     the arm's T = 1 chain; ESS/s divides by the arm's wall time.  Accuracy:
     per-parameter means of the two arms agree within 3 combined Monte Carlo
-    standard errors, and standard deviations within 5 %.  Also reported: the
+    standard errors (batch means of the ensemble mean), and standard
+    deviations within 5 %.  Also reported: the
     mean differences in batch-means standard errors (which see correlation
     between walkers) and the stretch arm's first half against its second half
     (a drift check).  keep_chains adds both arms' T = 1 chains to the result
@@ -594,8 +595,13 @@ def ess_comparison(loglike: Callable, logprior: Callable, x0: np.ndarray, betas,
         z_drift = np.abs(ch_plain[:h].reshape(-1, dim).mean(0) - ch_plain[h:].reshape(-1, dim).mean(0)) / se_drift
         zmax = float(np.nanmax(z))
         sd_rel = float(np.nanmax(np.abs(a2.std(0) / a1.std(0) - 1)))
+    zmax_bm = float(np.nanmax(z_bm))
+    # equal accuracy is judged on batch-means standard errors: the
+    # walker-averaged estimate misses correlation between walkers and
+    # understates the error of an ensemble's mean
     out["accuracy"] = {"max_mean_diff_in_se": round(zmax, 3), "max_sd_rel_diff": round(sd_rel, 4),
-                       "equal": bool(zmax < 3 and sd_rel < 0.05),
+                       "max_mean_diff_in_batch_means_se": round(zmax_bm, 3),
+                       "equal": bool(zmax_bm < 3 and sd_rel < 0.05),
                        "mean_diff_in_se": [round(float(v), 2) for v in z],
                        "mean_diff_in_batch_means_se": [round(float(v), 2) for v in z_bm],
                        "stretch_arm_half_vs_half_in_batch_means_se": [round(float(v), 2) for v in z_drift]}
