@@ -11,6 +11,13 @@ Prints one JSON line.  Extra objects:
   roofline      the dense interpolation + inner-product kernel, timed with HIP
                 events on its stream, against its roof;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same batch.
+
+Other modes (each prints its own JSON line):
+  --config cfg1 --walkers 1   the single-walker T_obs = 2^22 s case (latency);
+  --schedule-study            dense time per launch shape (uneven batch: --config cfg3);
+  --precision-study           FP32C ln L error per walker against FP64 at three SNRs, and speed;
+  --sampler SECONDS           ESS/s of stretch + learned proposal against stretch only;
+  --calibrate-copy MIB        a plain device copy, for scaling the traffic counters.
 """
 from __future__ import annotations
 
