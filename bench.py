@@ -13,8 +13,8 @@ Prints one JSON line.  Extra objects:
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same batch.
 
 Other modes (each prints its own JSON line):
-  --config cfg1 --walkers 1   the single-walker T_obs = 2^22 s case (latency);
-  --schedule-study            dense time per launch shape (uneven batch: --config cfg3);
+  --config tobs22 --walkers 1 the single-walker T_obs = 2^22 s case (latency);
+  --schedule-study            dense time per launch shape (uneven batch: --config uneven);
   --precision-study           FP32C ln L error per walker against FP64 at three SNRs, and speed;
   --sampler SECONDS           ESS/s of stretch + learned proposal against stretch only;
   --calibrate-copy MIB        a plain device copy, for scaling the traffic counters.
@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--walkers", type=int, default=1024)
-    ap.add_argument("--config", default="cfg2", choices=["cfg1", "cfg2", "cfg3"])
+    ap.add_argument("--config", default="tobs25", choices=["tobs22", "tobs25", "uneven"],
+                    help="workload: T_obs = 2^22 s grid, T_obs = 2^25 s grid (Gaussian ball), or uneven masses")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--cpu-threads", type=int, default=0,
@@ -89,11 +90,11 @@ def calibrate_copy(mib):
 
 def workload(name, walkers):
     from paper_2005_01827_amd import inputs
-    if name == "cfg1":
-        return inputs.config1(walkers)
-    if name == "cfg3":
-        return inputs.config3(walkers)
-    return inputs.config2(walkers)
+    if name == "tobs22":
+        return inputs.short_grid(walkers)
+    if name == "uneven":
+        return inputs.uneven_batch(walkers)
+    return inputs.year_grid(walkers)
 
 
 def band_bins(L, B):

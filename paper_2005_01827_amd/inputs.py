@@ -168,7 +168,7 @@ def ball(center: np.ndarray, n: int, rel: float, seed: int) -> np.ndarray:
     return to_physical(x)
 
 
-def config1(n_walkers: int = 1) -> Workload:
+def short_grid(n_walkers: int = 1) -> Workload:
     """Batch-1 latency case: T_obs = 2^22 s, f in [1e-4, 3e-2] Hz."""
     T = 2.0 ** 22
     grid = Grid.from_band(T, 1e-4, 3e-2)
@@ -176,23 +176,23 @@ def config1(n_walkers: int = 1) -> Workload:
     ext = _uniform_extrinsics(rng)
     inj = np.array([1e6, 0.2, 0.3, -0.2, luminosity_distance_gpc(2.0), *ext, 50.25])
     walkers = inj[None, :].copy() if n_walkers == 1 else ball(inj, n_walkers, 1e-3, 11)
-    return Workload("cfg1-batch1-Tobs2^22", grid, 0.9 * T, inj, walkers, noise_seed=101)
+    return Workload(f"{n_walkers}walkers-Tobs2^22", grid, 0.9 * T, inj, walkers, noise_seed=101)
 
 
-def config2(n_walkers: int = 1024) -> Workload:
+def year_grid(n_walkers: int = 1024) -> Workload:
     """Throughput case: 1024 walkers, T_obs = 2^25 s, f in [1e-5, 0.1] Hz."""
     T = 2.0 ** 25
     grid = Grid.from_band(T, 1e-5, 0.1)
     inj = np.array([3e6, 0.3, 0.3, -0.2, luminosity_distance_gpc(3.0), 2.14, 1.05, 2 * math.pi - 0.024,
                     0.62, 2.03, 50.25])
     walkers = ball(inj, n_walkers, 1e-3, 202)
-    return Workload(f"cfg2-{n_walkers}walkers-Tobs2^25", grid, YEAR_S, inj, walkers, noise_seed=2002)
+    return Workload(f"{n_walkers}walkers-Tobs2^25", grid, YEAR_S, inj, walkers, noise_seed=2002)
 
 
-def config3(n_walkers: int = 2048) -> Workload:
+def uneven_batch(n_walkers: int = 2048) -> Workload:
     """Uneven batch: log-uniform M_T in [1e5, 1e8], q ~ U[0.1,1], spins ~ U[-0.99,0.99],
     z ~ U[1,10], other parameters uniform over Table I; config-2 grid and data."""
-    base = config2(1)
+    base = year_grid(1)
     rng = np.random.Generator(np.random.PCG64(3))
     w = np.empty((n_walkers, 11))
     w[:, 0] = np.exp(rng.uniform(math.log(1e5), math.log(1e8), n_walkers))
@@ -204,7 +204,7 @@ def config3(n_walkers: int = 2048) -> Workload:
     for i in range(n_walkers):
         w[i, 5:10] = _uniform_extrinsics(rng)
     w[:, 10] = np.exp(rng.uniform(PRIOR_LO[10], PRIOR_HI[10], n_walkers))
-    return Workload("cfg3-2048-uneven-Tobs2^25", base.grid, base.t0, base.injection, w,
+    return Workload(f"uneven-{n_walkers}walkers-Tobs2^25", base.grid, base.t0, base.injection, w,
                     noise_seed=base.noise_seed)
 
 

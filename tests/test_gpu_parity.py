@@ -235,23 +235,23 @@ def _full_case(oracle, w, n_check, noise_seed, max_batch):
         L.close()
 
 
-def test_config1_batch1_full_grid(oracle):
+def test_tobs22_full_grid(oracle):
     print("case: T_obs=2^22 grid, injection + 64 perturbations", flush=True)
-    w = inputs.config1(65)
+    w = inputs.short_grid(65)
     w.walkers[0] = w.injection
     _full_case(oracle, w, 65, 101, 128)
 
 
 @pytest.mark.slow
-def test_config2_1024_walkers_sampled(oracle):
+def test_tobs25_1024_walkers_sampled(oracle):
     print("case: T_obs=2^25 grid, 1024 walkers, 12 checked", flush=True)
-    _full_case(oracle, inputs.config2(1024), 12, 2002, 1024)
+    _full_case(oracle, inputs.year_grid(1024), 12, 2002, 1024)
 
 
 @pytest.mark.slow
-def test_config3_uneven_sampled(oracle):
+def test_uneven_batch_sampled(oracle):
     print("case: T_obs=2^25 grid, 2048 uneven walkers, 16 checked", flush=True)
-    _full_case(oracle, inputs.config3(2048), 16, 2002, 2048)
+    _full_case(oracle, inputs.uneven_batch(2048), 16, 2002, 2048)
 
 
 def test_largest_batch_small_grid(oracle):
@@ -286,7 +286,7 @@ def test_largest_knot_count_full_grid(oracle):
     sees the shortest intervals at full size."""
     import dataclasses
     print("case: T_obs=2^25 grid, ns = 1024, 6 modes, 16 walkers, 3 checked", flush=True)
-    w = dataclasses.replace(inputs.config2(16), ns=1024)
+    w = dataclasses.replace(inputs.year_grid(16), ns=1024)
     _full_case(oracle, w, 3, 2003, 16)
 
 
@@ -331,11 +331,11 @@ def test_fp32c_small_grid(oracle):
 
 
 @pytest.mark.slow
-def test_fp32c_config2_sampled(oracle):
+def test_fp32c_tobs25_sampled(oracle):
     import torch
     from paper_2005_01827_amd import mbh
     print("case: FP32C, T_obs=2^25 grid, 1024 walkers, 12 checked", flush=True)
-    w = inputs.config2(1024)
+    w = inputs.year_grid(1024)
     g = w.grid
     psd = inputs.psd_aet(g.freqs)
     d = oracle.template(w.injection, g, w.modes, w.ns, w.t0) + inputs.noise(g, psd, 2002)
@@ -349,5 +349,5 @@ def test_fp32c_config2_sampled(oracle):
     ref = oracle.loglike(w.walkers[idx], g, d, psd, w.modes, w.ns, w.t0, nthreads=min(16, os.cpu_count()))
     err = np.abs(got[idx] - ref[:, 0])
     bound = _fp32_bound(ref)
-    print(f"[fp32c-cfg2] max |dlnL| = {err.max():.3e}  SNR ~ {np.sqrt(ref[:, 4:7].sum(1)).mean():.0f}", flush=True)
+    print(f"[fp32c-tobs25] max |dlnL| = {err.max():.3e}  SNR ~ {np.sqrt(ref[:, 4:7].sum(1)).mean():.0f}", flush=True)
     assert np.all(err <= bound)

@@ -160,6 +160,6 @@ def test_psd_positive_and_T_suppressed():
 
 
 def test_grid_sizes_of_the_workloads():
-    assert inputs.config1().grid.n == 125410 and inputs.config1().grid.k0 == 420
-    g2 = inputs.config2(1).grid
+    assert inputs.short_grid().grid.n == 125410 and inputs.short_grid().grid.k0 == 420
+    g2 = inputs.year_grid(1).grid
     assert g2.n == 3355108 and g2.k0 == 336
