@@ -208,6 +208,42 @@ def uneven_batch(n_walkers: int = 2048) -> Workload:
                     noise_seed=base.noise_seed)
 
 
+def table2_binaries() -> dict:
+    """Injection parameters of the seven test binaries of Sec. IV (Table II),
+    as physical parameters [11] keyed by binary number.
+
+    The table prints rounded values, used as printed; q is taken as the
+    fraction it names (1/3, 1/5, 7/10).  A negative ecliptic longitude is
+    mapped into the prior range [0, 2 pi).  t_ref is relative to t0 = 1 yr,
+    as for the other workloads on the 2^25-s grid.  Binaries 2 and 3 repeat
+    Binary 1 (2 has no noise; 3 keeps the spins fixed while sampling).
+    """
+    b13 = [2e6, 1.0 / 3.0, 0.0, 0.0, 36.59, 2.14, 1.05, -0.024, 0.62, 2.03, 50.25]
+    rows = {
+        1: b13, 2: b13, 3: b13,
+        4: [2e6, 1.0 / 3.0, 0.85, 0.88, 36.59, 2.14, 1.05, -0.024, 0.62, 2.03, 50.25],
+        5: [2e6, 1.0 / 3.0, -0.83, -0.89, 36.59, 2.14, 1.05, -0.024, 0.62, 2.03, 50.25],
+        6: [4e7, 1.0 / 5.0, 0.0, 0.0, 15.93, 3.10, 1.34, 4.21, -0.73, 0.14, 23.93],
+        7: [3e5, 7.0 / 10.0, 0.0, 0.0, 70.58, 1.22, 1.32, 2.24, -0.22, 2.73, 94.33],
+    }
+    out = {}
+    for b, r in rows.items():
+        th = np.array(r, dtype=np.float64)
+        th[7] = th[7] % (2.0 * math.pi)
+        out[b] = th
+    return out
+
+
+def table2_workload(binary: int) -> Workload:
+    """One Table II binary on the 2^25-s grid (f in [1e-5, 0.1] Hz, t0 = 1 yr);
+    the single walker sits on the injection.  Binaries 2 and 7 were injected
+    without noise in Sec. IV; the others carry a noise seed."""
+    base = year_grid(1)
+    inj = table2_binaries()[binary]
+    seed = None if binary in (2, 7) else 7000 + binary
+    return Workload(f"binary{binary}-Tobs2^25", base.grid, base.t0, inj, inj[None, :].copy(), noise_seed=seed)
+
+
 def small_config(n_walkers: int = 8, seed: int = 7) -> Workload:
     """A small grid the oracle finishes in well under a second per walker:
     T_obs = 2^20 s, f in [2e-4, 2e-2] Hz, M_T = 2e6, q = 1/3."""
