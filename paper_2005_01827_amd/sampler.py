@@ -60,6 +60,83 @@ def ladder(n_rungs: int, ratio: float = 2.04807, top_infinite: bool = True) -> n
     return betas
 
 
+def adapt_ladder(betas: np.ndarray, swap_frac: np.ndarray, t: int, lag: float, time_scale: float) -> np.ndarray:
+    """One step of the adaptive-tempering dynamics (Vousden, Farr and Mandel
+    2016, used by the paper through ptemcee, Sec. III.B).
+
+    betas[N] with betas[0] = 1 and betas[-1] = 0 (T_N = infinity);
+    swap_frac[N-1] is this step's swap acceptance between rungs k and k+1.
+    Interior rung i (1 <= i <= N-2) has the gap g_i = T_i - T_{i-1}; its
+    logarithm moves by kappa (swap_frac[i-1] - swap_frac[i]), so a pair that
+    swaps more often than the pair above it widens, and the acceptances even
+    out.  kappa = (1/time_scale) lag / (t + lag) decays with the step t.
+    The gaps are rebuilt from T_0 = 1 upward; the top rung stays at beta = 0.
+    """
+    betas = np.asarray(betas, dtype=np.float64)
+    kappa = lag / (t + lag) / time_scale
+    T = 1.0 / betas[:-1]                       # finite rungs T_0 = 1 .. T_{N-2}
+    gaps = np.diff(T) * np.exp(kappa * (swap_frac[:-1] - swap_frac[1:]))
+    out = betas.copy()
+    out[1:-1] = 1.0 / (T[0] + np.cumsum(gaps))
+    return out
+
+
+def ti_evidence(betas, mean_logl):
+    """Thermodynamic-integration evidence from parallel-tempered chains:
+    ln Z = integral over beta in [0, 1] of <ln L>_beta, where <.>_beta is the
+    mean under the tempered posterior proportional to L^beta pi (at beta = 0
+    the prior).  The integral is the trapezoid rule over the ladder's betas;
+    the error estimate is the difference from the same rule on every other
+    rung (the coarser ladder), as is usual for this estimator.
+
+    betas[N] and mean_logl[N] in any order; returns (ln Z, error estimate).
+    """
+    b = np.asarray(betas, dtype=np.float64)
+    m = np.asarray(mean_logl, dtype=np.float64)
+    o = np.argsort(b)
+    b, m = b[o], m[o]
+    if b[0] != 0.0 or b[-1] != 1.0:
+        raise ValueError("the ladder must span beta = 0 (T = infinity) to beta = 1")
+
+    def trap(bb, mm):
+        return float(np.sum(np.diff(bb) * 0.5 * (mm[1:] + mm[:-1])))
+
+    lnz = trap(b, m)
+    keep = np.arange(0, len(b), 2)
+    if keep[-1] != len(b) - 1:
+        keep = np.append(keep, len(b) - 1)
+    coarse = trap(b[keep], m[keep])
+    return lnz, abs(lnz - coarse)
+
+
+def fix_coordinates(fn: Callable, dim: int, fixed: dict) -> Callable:
+    """Wrap fn(x[N][dim]) as a function of the free coordinates only: the
+    coordinates in 'fixed' (index -> value) are inserted before the call.
+    Sec. IV samples Binary 3 with the two spins held at their injected values
+    (D = 9 instead of 11); fix_coordinates(loglike, 11, {2: a1, 3: a2}) and the
+    same for the prior give that sampler.  The wrapped function has
+    .expand(x_free) -> x_full and .free (the free indices)."""
+    free = np.array([i for i in range(dim) if i not in fixed], dtype=np.int64)
+    idx = np.array(sorted(fixed), dtype=np.int64)
+    vals = np.array([fixed[i] for i in sorted(fixed)], dtype=np.float64)
+
+    def expand(xf):
+        xf = np.atleast_2d(np.asarray(xf, dtype=np.float64))
+        if xf.shape[1] != len(free):
+            raise ValueError(f"expected {len(free)} free coordinates, got {xf.shape[1]}")
+        x = np.empty((xf.shape[0], dim))
+        x[:, free] = xf
+        x[:, idx] = vals
+        return x
+
+    def wrapped(xf):
+        return fn(expand(xf))
+
+    wrapped.expand = expand
+    wrapped.free = free
+    return wrapped
+
+
 # ---------------------------------------------------------------------------
 # Autocorrelation (Sec. III.C)
 # ---------------------------------------------------------------------------
@@ -145,10 +222,24 @@ class PTSampler:
       and .logq(x) -> logq (or .propose(x_old, rng) -> (x, logq, logq_old));
       used with probability p_flow at rungs with beta >= flow_beta_min
       (default: the beta = 1 rungs whose posterior it was trained on).
+    adapt: adaptive tempering (Sec. III.B uses ptemcee's; the dynamics are
+      those of Vousden, Farr and Mandel 2016): after each round of swaps every
+      interior rung i moves so that S_i = ln(T_i - T_{i-1}) changes by
+      kappa(t) (A_{i-1,i} - A_{i,i+1}), the difference of this step's swap
+      acceptance fractions below and above it, with
+      kappa(t) = (1/adapt_time) adapt_lag / (t + adapt_lag).  The coldest
+      rung (T = 1) and the top rung stay where they are; the top must be
+      T = infinity (beta = 0), as in the paper, so that the ladder stays
+      ordered.  Adaptation breaks detailed balance while it acts: switch it
+      off (sampler.adapt = False) before keeping samples.
+    record_logl: keep ln L of every rung and walker after each step in
+      self.logl_history (for the thermodynamic-integration evidence).
     """
 
     def __init__(self, loglike: Callable, logprior: Callable, betas, n_walkers: int, dim: int,
-                 a: float = 1.15, seed: int = 0, proposal=None, p_flow: float = 0.0, flow_beta_min: float = 1.0):
+                 a: float = 1.15, seed: int = 0, proposal=None, p_flow: float = 0.0, flow_beta_min: float = 1.0,
+                 adapt: bool = False, adapt_lag: float = 10000.0, adapt_time: float = 100.0,
+                 record_logl: bool = False):
         if n_walkers % 2 or n_walkers < 4:
             raise ValueError("n_walkers must be even and >= 4")
         self.loglike = loglike
@@ -162,6 +253,14 @@ class PTSampler:
         self.proposal = proposal
         self.p_flow = p_flow
         self.flow_beta_min = flow_beta_min   # the proposal models the beta = 1 posterior
+        if adapt and (self.nt < 3 or self.betas[-1] != 0.0 or self.betas[0] != 1.0):
+            raise ValueError("adaptive tempering needs >= 3 rungs from beta = 1 to beta = 0 (T = infinity)")
+        self.adapt = adapt
+        self.adapt_lag = adapt_lag
+        self.adapt_time = adapt_time
+        self.record_logl = record_logl
+        self.logl_history: list = []
+        self.swap_frac = np.zeros(max(self.nt - 1, 0))   # this step's swap acceptance per adjacent pair
         self.state: Optional[PTState] = None
         self.n_like_calls = 0
         self.like_seconds = 0.0
@@ -234,6 +333,10 @@ class PTSampler:
             st.flow_accepted += int((accept & use_flow).sum())
             st.flow_proposed += int(use_flow.sum())
         self._swap()
+        if self.adapt:
+            self.betas = adapt_ladder(self.betas, self.swap_frac, st.step, self.adapt_lag, self.adapt_time)
+        if self.record_logl:
+            self.logl_history.append(st.logl.copy())
         st.step += 1
         st.rng_state = self.rng.bit_generator.state
         return st
@@ -258,6 +361,7 @@ class PTSampler:
                 arr[i - 1, a_j] = tmp
             st.swaps_accepted[i - 1] += int(acc.sum())
             st.swaps_proposed[i - 1] += self.nw
+            self.swap_frac[i - 1] = acc.mean()
 
     def run(self, n_steps: int, thin: int = 1, callback=None):
         """Run n_steps; return the T = 1 chain [n_steps/thin][W][D]."""
@@ -299,6 +403,7 @@ class PTSampler:
             self.proposal.mu = z["flow_mu"].copy()
             self.proposal.sd = z["flow_sd"].copy()
             self.p_flow = float(z["p_flow"])
+        self.betas = z["betas"].copy()        # an adapted ladder resumes where it stood
         self.state = PTState(x=z["x"].copy(), logl=z["logl"].copy(), logp=z["logp"].copy(), step=int(z["step"]),
                              rng_state=rng_state, accepted=z["accepted"].copy(), proposed=z["proposed"].copy(),
                              swaps_accepted=z["swaps_accepted"].copy(), swaps_proposed=z["swaps_proposed"].copy(),

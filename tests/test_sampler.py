@@ -170,3 +170,129 @@ def test_checkpoint_resume_is_bit_identical(tmp_path):
     tail_b = b.run(40)
     assert np.array_equal(tail_a, tail_b)
     assert np.array_equal(a.state.logl, b.state.logl)
+
+
+# ---------------------------------------------------------------------------
+# Thermodynamic-integration evidence, adaptive tempering, fixed coordinates
+# ---------------------------------------------------------------------------
+D_BOX, SIG_BOX, A_BOX = 2, 0.5, 5.0
+
+
+def _box_gauss():
+    """Isotropic Gaussian likelihood exp(-|x|^2 / (2 sig^2)) under a uniform
+    prior on [-a, a]^D: Z = (sig sqrt(2 pi) erf(a / (sig sqrt 2)) / (2a))^D."""
+    def ll(x):
+        return -0.5 * np.sum(np.atleast_2d(x) ** 2, axis=1) / SIG_BOX ** 2
+
+    def lp(x):
+        x = np.atleast_2d(x)
+        return np.where(np.all(np.abs(x) <= A_BOX, axis=1), 0.0, -np.inf)
+    lnz = D_BOX * math.log(SIG_BOX * math.sqrt(2 * math.pi) * math.erf(A_BOX / (SIG_BOX * math.sqrt(2))) / (2 * A_BOX))
+    return ll, lp, lnz
+
+
+def _box_gauss_mean_logl(beta):
+    """<ln L> under L^beta pi: each coordinate is a normal of scale sig/sqrt(beta)
+    truncated to [-a, a], whose second moment is s^2 (1 - 2 c phi(c) / (2 Phi(c) - 1)),
+    c = a / s; at beta = 0 the prior's a^2 / 3."""
+    if beta == 0.0:
+        ex2 = A_BOX ** 2 / 3
+    else:
+        s = SIG_BOX / math.sqrt(beta)
+        c = A_BOX / s
+        ex2 = s * s * (1 - 2 * c * stats.norm.pdf(c) / (2 * stats.norm.cdf(c) - 1))
+    return -D_BOX * ex2 / (2 * SIG_BOX ** 2)
+
+
+def test_ti_evidence_quadrature_converges_to_closed_form():
+    _, _, exact = _box_gauss()
+    errs = []
+    for nr, ratio in ((21, 2.0), (30, 1.5), (60, 1.2)):
+        b = S.ladder(nr, ratio)
+        lnz, est = S.ti_evidence(b, [_box_gauss_mean_logl(x) for x in b])
+        errs.append(abs(lnz - exact))
+        assert errs[-1] < est, (nr, lnz, exact, est)
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 0.02
+    # the ladder's order does not matter; it must span beta = 0 .. 1
+    b = S.ladder(30, 1.5)
+    m = [_box_gauss_mean_logl(x) for x in b]
+    assert S.ti_evidence(b[::-1], m[::-1])[0] == S.ti_evidence(b, m)[0]
+    with pytest.raises(ValueError):
+        S.ti_evidence(S.ladder(5, top_infinite=False), np.zeros(5))
+
+
+def test_parallel_tempering_evidence_matches_closed_form():
+    ll, lp, exact = _box_gauss()
+    betas = S.ladder(30, 1.5)
+    smp = S.PTSampler(ll, lp, betas, 32, D_BOX, a=2.0, seed=3, record_logl=True)
+    smp.initialize(np.random.default_rng(4).uniform(-A_BOX, A_BOX, (30, 32, D_BOX)))
+    smp.run(300)
+    smp.logl_history.clear()
+    smp.run(1500)
+    lnz, est = S.ti_evidence(smp.betas, np.mean(np.array(smp.logl_history), axis=(0, 2)))
+    quad, _ = S.ti_evidence(betas, [_box_gauss_mean_logl(x) for x in betas])
+    assert abs(lnz - quad) < 0.05           # Monte Carlo part: the chains' <ln L>_beta
+    assert abs(lnz - exact) < est + 0.05    # and the whole estimate, within its quadrature error
+
+
+def test_adapt_ladder_rule():
+    b = S.ladder(6)
+    # equal acceptances: the ladder does not move
+    assert np.array_equal(S.adapt_ladder(b, np.full(5, 0.4), 0, 100.0, 10.0), b)
+    A = np.array([0.9, 0.3, 0.5, 0.5, 0.2])
+    nb = S.adapt_ladder(b, A, 50, 100.0, 10.0)
+    kappa = 100.0 / 150.0 / 10.0
+    T, nT = 1 / b[:-1], 1 / nb[:-1]
+    assert nb[0] == 1.0 and nb[-1] == 0.0 and np.all(np.diff(nb) < 0)
+    assert np.allclose(np.diff(nT) / np.diff(T), np.exp(kappa * (A[:-1] - A[1:])), rtol=1e-13)
+    with pytest.raises(ValueError):
+        S.PTSampler(lambda x: x[:, 0], lambda x: 0 * x[:, 0], S.ladder(4, top_infinite=False), 8, 2, adapt=True)
+
+
+def test_adaptive_tempering_evens_swap_acceptance(tmp_path):
+    ll, lp, _ = _box_gauss()
+    spread = {}
+    for adapt in (False, True):
+        smp = S.PTSampler(ll, lp, S.ladder(10), 32, D_BOX, a=2.0, seed=5, adapt=adapt, adapt_lag=1000,
+                          adapt_time=20)
+        smp.initialize(np.random.default_rng(6).uniform(-A_BOX, A_BOX, (10, 32, D_BOX)))
+        smp.run(2000)
+        smp.adapt = False
+        a0, p0 = smp.state.swaps_accepted.copy(), smp.state.swaps_proposed.copy()
+        smp.run(1000)
+        fr = (smp.state.swaps_accepted - a0) / (smp.state.swaps_proposed - p0)
+        spread[adapt] = fr.max() - fr.min()
+        assert smp.betas[0] == 1.0 and smp.betas[-1] == 0.0 and np.all(np.diff(smp.betas) < 0)
+    assert spread[True] < 0.5 * spread[False], spread
+    # a checkpoint keeps the adapted ladder
+    path = os.path.join(tmp_path, "adapted.npz")
+    smp.save(path)
+    other = S.PTSampler(ll, lp, S.ladder(10), 32, D_BOX, seed=1)
+    other.load(path)
+    assert np.array_equal(other.betas, smp.betas)
+
+
+def test_fixed_coordinates_sample_the_conditional():
+    """Holding coordinate 2 of a 3-D Gaussian fixed (as Sec. IV holds the
+    spins of Binary 3) samples the conditional Gaussian of the other two."""
+    dim = 3
+    mu, cov, ll = _gauss_target(dim, 21)
+    c = mu[2] + 0.7
+    flat = lambda x: np.zeros(len(np.atleast_2d(x)))
+    ll2 = S.fix_coordinates(ll, dim, {2: c})
+    lp2 = S.fix_coordinates(flat, dim, {2: c})
+    assert list(ll2.free) == [0, 1]
+    assert np.array_equal(ll2.expand(np.array([[1.0, 2.0]])), [[1.0, 2.0, c]])
+    s12 = cov[:2, 2]
+    mu_c = mu[:2] + s12 * (c - mu[2]) / cov[2, 2]
+    cov_c = cov[:2, :2] - np.outer(s12, s12) / cov[2, 2]
+    smp = S.PTSampler(ll2, lp2, [1.0], 32, 2, a=2.0, seed=22)
+    smp.initialize((mu_c + 0.1 * np.random.default_rng(23).standard_normal((32, 2)))[None])
+    smp.run(500)
+    chain = smp.run(4000)
+    n_eff, _, _ = S.ess(chain)
+    flat_s = chain.reshape(-1, 2)
+    assert np.all(np.abs(flat_s.mean(0) - mu_c) < 5 * np.sqrt(np.diag(cov_c) / n_eff))
+    assert np.allclose(np.cov(flat_s.T), cov_c, atol=0.1 * np.abs(cov_c).max())
+    with pytest.raises(ValueError):
+        ll2(np.zeros((4, 3)))
