@@ -18,6 +18,7 @@ Other modes (each prints its own JSON line):
   --precision-study           FP32C ln L error per walker against FP64 at three SNRs, and speed;
   --sampler SECONDS           ESS/s of stretch + learned proposal against stretch only;
   --snr-table                 per-mode SNRs of the Table II binaries (Table III), zero noise and in noise;
+  --knot-study                ln L accuracy and speed against the number of sparse knots per mode;
   --calibrate-copy MIB        a plain device copy, for scaling the traffic counters.
 """
 from __future__ import annotations
@@ -40,7 +41,7 @@ FP64_PEAK_TFLOPS = 78.6            # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 
 FLOPS_PER_MODE_BIN = 111           # 8 cubics 48, e^{i phi} 37, A e^{i phi} 2, 3 complex MACs 24
 FLOPS_PER_WALKER_BIN = 21          # per channel: d-h 2, |r|^2 w 5 (ln L needs only the residual sums)
 BYTES_PER_WALKER_BIN = 72          # d (3 x complex128) + w (3 x float64), streamed per walker
-KERNEL_REV = "dense-v20"           # traffic counters are only reused for this kernel revision
+KERNEL_REV = "dense-v21"           # traffic counters are only reused for this kernel revision
 
 
 def parse():
@@ -75,6 +76,9 @@ def parse():
     ap.add_argument("--snr-table", action="store_true",
                     help="instead of the throughput line, decompose the SNR of the Table II binaries by mode "
                          "(all modes and each mode alone), in zero noise and in noise; one JSON line")
+    ap.add_argument("--knot-study", action="store_true",
+                    help="instead of the throughput line, evaluate the batch with 64..1024 sparse knots per mode: "
+                         "speed, and ln L against 1024 knots and against the oracle at 2048; one JSON line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) and exit; used to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -339,8 +343,64 @@ def snr_table(args):
     print(json.dumps(result), flush=True)
 
 
+def knot_study(args):
+    """Sparse-grid density (Sec. II.A: each function on about 2^10 points):
+    ln L of the batch with n_s = 64 .. 1024 knots per mode, its change
+    against n_s = 1024, and, on a sample of walkers, against the FP64 oracle
+    at 2048 knots (the converged spline); time per sweep and of the dense
+    kernel at each n_s."""
+    import torch
+    from paper_2005_01827_amd import inputs, mbh
+    w = workload(args.config, args.walkers)
+    g = w.grid
+    B = len(w.walkers)
+    psd = inputs.psd_aet(g.freqs)
+    L0 = mbh.Likelihood(g, np.zeros((3, g.n), complex), psd, w.modes, 1024, w.t0, max_batch=1)
+    data = L0.template(w.injection).cpu().numpy() + inputs.noise(g, psd, w.noise_seed)
+    L0.close()
+    p_dev = torch.as_tensor(w.walkers, dtype=torch.float64, device="cuda")
+    out = torch.empty(B, dtype=torch.float64, device="cuda")
+    res, rows = {}, []
+    for ns in (64, 128, 256, 512, 1024):
+        L = mbh.Likelihood(g, data, psd, w.modes, ns, w.t0, max_batch=B)
+        L.loglike(p_dev, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            L.loglike(p_dev, out=out)
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t0) * 1e3 / 5
+        L.set_timing(True)
+        for _ in range(3):
+            L.loglike(p_dev, out=out)
+        dms, cnt = L.get_timing()
+        L.set_timing(False)
+        res[ns] = out.cpu().numpy().copy()
+        L.close()
+        rows.append({"n_sparse": ns, "ms_per_step": round(step_ms, 3), "evals_per_s": round(B / (step_ms * 1e-3), 1),
+                     "dense_ms": round(dms / max(cnt, 1), 3)})
+        print(f"# {json.dumps(rows[-1])}", file=sys.stderr, flush=True)
+    for r in rows:
+        r["max_abs_dlnL_vs_1024"] = float(np.max(np.abs(res[r["n_sparse"]] - res[1024])))
+    result = {"metric": "ln L accuracy and speed against sparse knots per mode", "unit": "abs ln L; evals/s",
+              "n_gpus": 1, "config": {"workload": w.name, "walkers": B, "dense_bins": g.n}, "rows": rows}
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        O.build()
+        idx = np.linspace(0, B - 1, min(4, B)).astype(int)
+        ref = O.loglike(w.walkers[idx], g, data, psd, w.modes, 2048, w.t0,
+                        nthreads=min(16, os.cpu_count() or 1))[:, 0]
+        for r in rows:
+            r["max_abs_dlnL_vs_oracle_2048_sample"] = float(np.max(np.abs(res[r["n_sparse"]][idx] - ref)))
+        result["oracle_sample_walkers"] = int(len(idx))
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
+    if args.knot_study and args.gpus == 1:
+        knot_study(args)
+        return
     if args.snr_table and args.gpus == 1:
         snr_table(args)
         return

@@ -293,29 +293,32 @@ struct DenseArgs {
 
 __device__ __forceinline__ int uni_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// e^{i phi} = e^{i q pi/128} e^{i r}.  t = phi 128/pi is rounded to the
+// e^{i phi} = e^{i q pi/512} e^{i r}.  t = phi 512/pi is rounded to the
 // integer q by adding and subtracting 1.5 2^52 (exact for |t| < 2^51), which
-// leaves q mod 2^32 in the low word of the sum; r = phi - q pi/128 with a
-// two-part pi/128 (two FMAs), so |r| <= pi/256 up to rounding.  On that range
-// the Taylor polynomials of sin r (to r^5) and cos r (to r^6) truncate below
-// 1e-17, and e^{i q pi/128} is entry q mod 256 of a table of cos and sin of
-// j pi/128, staged in LDS: one per-lane LDS read replaces the quadrant logic
+// leaves q mod 2^32 in the low word of the sum; r = phi - q pi/512 with a
+// two-part pi/512 (two FMAs), so |r| <= pi/1024 up to rounding.  On that
+// range sin r = r - r^3/6 truncates below 2.3e-15 and cos r = 1 - r^2/2 +
+// r^4/24 below 1.2e-18, far under the rounding of phi itself (the phase of a
+// mode reaches 2 pi f t_c, about 1e6 rad, whose last bit is 1e-10 rad);
+// e^{i q pi/512} is entry q mod 1024 of a table of cos and sin of j pi/512,
+// staged in LDS (16 KB): one per-lane LDS read replaces the quadrant logic
 // and most of the polynomial of a reduction modulo pi/2.
 //
 // Device table layout (filled once per context): kCisN constants, then the
 // kRotN (cos, sin) pairs.
-constexpr int kRotN = 256;
+constexpr int kRotN = 1024;
 constexpr int kCisN = 8;
-constexpr int kCisPoly = 6;      // constants used by cis(): 128/pi, pi/128 (two parts), sin and cos terms
+constexpr int kCisPoly = 5;      // constants used by cis(): 512/pi, pi/512 (two parts), -1/6, 1/24
 constexpr int kTwoOverPi = 6;    // 2/pi, for the quarter-turn reduction of the FP32 stage
 constexpr double kRoundShift = 6755399441055744.0;   // 1.5 * 2^52
 static_assert(kCisN % 2 == 0 && kCisN + 2 * kRotN <= kCisTabDoubles, "rotation table must fit the device table");
 const double kCisHost[kCisN] = {
-    40.743665431525205956,                                    // 128/pi
-    3.141592653589793116 / 128.0,                             // pi/128 rounded to double (exact scaling of pi)
-    1.2246467991473532e-16 / 128.0,                           // pi/128 - the above
-    1.0 / 120.0, -1.0 / 6.0,                                  // sin: r^5, r^3
-    -1.0 / 720.0,                                             // cos: r^6 (r^4 and r^2 are 1/24 and -1/2)
+    162.97466172610082383,                                    // 512/pi
+    3.141592653589793116 / 512.0,                             // pi/512 rounded to double (exact scaling of pi)
+    1.2246467991473532e-16 / 512.0,                           // pi/512 - the above
+    -1.0 / 6.0,                                               // sin: r^3
+    1.0 / 24.0,                                               // cos: r^4
+    0.0,
     0.63661977236758134308,                                   // 2/pi
     0.0};
 
@@ -337,7 +340,7 @@ __device__ __forceinline__ int lane_zero()
     return z;
 }
 
-// The polynomial and reduction constants are held in VGPRs (20 of them): in
+// The polynomial and reduction constants are held in VGPRs: in
 // scalar registers they pushed the per-mode interval state and the
 // coefficient blocks into SGPR spills, whose reloads cost more VALU issue
 // than the VGPRs cost occupancy.  The rotation table is copied to LDS by the
@@ -361,10 +364,8 @@ __device__ __forceinline__ void cis(const CisConst &K, double phi, double &sn, d
     double r = fma(-q, K.k[1], phi);
     r = fma(-q, K.k[2], r);
     const double r2 = r * r;
-    const double ps = fma(K.k[3], r2, K.k[4]);
-    const double sr = fma(r * r2, ps, r);
-    double pc = fma(K.k[5], r2, 1.0 / 24.0);
-    pc = fma(pc, r2, -0.5);
+    const double sr = fma(r * r2, K.k[3], r);
+    const double pc = fma(K.k[4], r2, -0.5);
     const double cr = fma(r2, pc, 1.0);
     cs = fma(e.x, cr, -(e.y * sr));
     sn = fma(e.y, cr, e.x * sr);
@@ -1010,7 +1011,7 @@ __global__ void k_coef32(const double *__restrict__ coef, float *__restrict__ co
 
 const double *cis_table_host(int *n)
 {
-    // cos and sin of j pi/128 from long double, rounded once to double;
+    // cos and sin of j pi/512 from long double, rounded once to double;
     // built on first use (thread-safe static initialisation)
     struct Tab {
         double v[kCisN + 2 * kRotN];

@@ -28,7 +28,7 @@ constexpr int kMaxDenseSteps = 32;
 constexpr int kMinDenseSteps = 2;
 constexpr int kBinsPerLane = 2;   // bins per lane per step of the FP64 dense kernel
 static_assert(kMinDenseSteps % kBinsPerLane == 0, "steps per wavefront must be a multiple of the bins per lane");
-constexpr int kCisTabDoubles = 1024;  // device table of the dense-stage sin/cos constants and rotations
+constexpr int kCisTabDoubles = 2064;  // device table of the dense-stage sin/cos constants and rotations
 constexpr int kPartials = 9;       // R_c, DH_c, HH_c for c = A, E, T
 
 // Per-walker constants of the waveform model (built by the source kernel).

@@ -80,3 +80,22 @@ def test_rejects_bad_knots(oracle):
         oracle.spline_coeffs(np.array([0.0, 1.0, 1.0, 2.0]), np.zeros(4))
     with pytest.raises(ValueError):
         oracle.spline_coeffs(np.array([0.0, 1.0, 2.0]), np.zeros(3))
+
+
+def test_loglike_converges_at_fourth_order_in_knot_spacing(oracle):
+    """Sec. II.A represents each function on a sparse grid (about 2^10 points)
+    and splines it to the data bins.  A cubic spline with not-a-knot ends
+    interpolates a smooth function with error O(h^4), so ln L at n_s knots
+    approaches its dense-knot limit with the error falling about 16-fold per
+    doubling of n_s; a lower-order end condition or interval lookup would
+    show a smaller ratio."""
+    from paper_2005_01827_amd import inputs
+    w = inputs.small_config(4)
+    g = w.grid
+    psd = inputs.psd_aet(g.freqs)
+    d = oracle.template(w.injection, g, w.modes, 2048, w.t0) + inputs.noise(g, psd, 5)
+    ref = oracle.loglike(w.walkers, g, d, psd, w.modes, 2048, w.t0)[:, 0]
+    errs = [np.abs(oracle.loglike(w.walkers, g, d, psd, w.modes, ns, w.t0)[:, 0] - ref).max()
+            for ns in (128, 256, 512, 1024)]
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all((ratios > 12) & (ratios < 22)), ratios
