@@ -19,6 +19,7 @@ Other modes (each prints its own JSON line):
   --sampler SECONDS           ESS/s of stretch + learned proposal against stretch only;
   --snr-table                 per-mode SNRs of the Table II binaries (Table III), zero noise and in noise;
   --knot-study                ln L accuracy and speed against the number of sparse knots per mode;
+  --points-study              time per likelihood against the number of frequency points (Fig. 3);
   --calibrate-copy MIB        a plain device copy, for scaling the traffic counters.
 """
 from __future__ import annotations
@@ -79,6 +80,10 @@ def parse():
     ap.add_argument("--knot-study", action="store_true",
                     help="instead of the throughput line, evaluate the batch with 64..1024 sparse knots per mode: "
                          "speed, and ln L against 1024 knots and against the oracle at 2048; one JSON line")
+    ap.add_argument("--points-study", action="store_true",
+                    help="instead of the throughput line, time one likelihood against the number of frequency "
+                         "points (T_obs = 2^18 .. 2^25 s, f up to 0.15 Hz): one walker, a 1024-walker batch, and the "
+                         "FP64 oracle on one core; one JSON line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) and exit; used to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -396,8 +401,78 @@ def knot_study(args):
     print(json.dumps(result), flush=True)
 
 
+def points_study(args):
+    """Time per likelihood against the number of frequency points, as in
+    Fig. 3 of the paper (waveform, response and ln L in all three channels).
+    Grids T_obs = 2^p s, p = 18 .. 25, over [1e-5, 0.15] Hz (0.15 Hz is the
+    Nyquist frequency of a 0.3 Hz sampling, the paper's reference data
+    rate), so n runs from 3.9e4 to 5.0e6 points.  The source is the 2^25-s
+    workload's injection, merging at t0 = 0.9 T_obs (1 yr at 2^25 s); the
+    batch is a Gaussian ball around it.  Per grid: one walker through the
+    graph-launched entry point, a 1024-walker batch (time per sweep / 1024),
+    and the FP64 oracle on one core for one walker; the ratio of the oracle's
+    time to the GPU's is the paper's "effective number of CPUs"."""
+    import torch
+    from paper_2005_01827_amd import inputs, mbh
+    base = inputs.year_grid(1)
+    rows = []
+    for p2 in range(18, 26):
+        T = 2.0 ** p2
+        g = inputs.Grid.from_band(T, 1e-5, 0.15)
+        t0 = inputs.YEAR_S if p2 == 25 else 0.9 * T
+        psd = inputs.psd_aet(g.freqs)
+        inj = base.injection
+        walkers = inputs.ball(inj, 1024, 1e-3, 202)
+        L0 = mbh.Likelihood(g, np.zeros((3, g.n), complex), psd, base.modes, base.ns, t0, max_batch=1)
+        data = L0.template(inj).cpu().numpy() + inputs.noise(g, psd, 2002)
+        L0.close()
+        row = {"T_obs_s": T, "points": g.n}
+        for B, reps in ((1, 200), (1024, 10)):
+            L = mbh.Likelihood(g, data, psd, base.modes, base.ns, t0, max_batch=B)
+            p_dev = torch.as_tensor(walkers[:B], dtype=torch.float64, device="cuda")
+            out = torch.empty(B, dtype=torch.float64, device="cuda")
+            if B > 1:
+                L.autotune(p_dev, reps=3)
+            for _ in range(5):
+                L.loglike(p_dev, out=out)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                L.loglike(p_dev, out=out)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3 / reps
+            L.close()
+            if B == 1:
+                row["gpu_ms_per_eval_batch1"] = round(ms, 4)
+            else:
+                row["gpu_ms_per_eval_batch1024"] = round(ms / B, 5)
+        if not args.no_cpu_baseline:
+            from oracle import oracle as O
+            O.build()
+            O.loglike(walkers[:1], g, data, psd, base.modes, base.ns, t0, nthreads=1)
+            t = time.perf_counter()
+            n_rep = 3 if g.n < 1_000_000 else 1
+            for _ in range(n_rep):
+                O.loglike(walkers[:1], g, data, psd, base.modes, base.ns, t0, nthreads=1)
+            cpu_ms = (time.perf_counter() - t) * 1e3 / n_rep
+            row["cpu_baseline_ms_per_eval_1core"] = round(cpu_ms, 2)
+            row["effective_cpus_batch1"] = round(cpu_ms / row["gpu_ms_per_eval_batch1"], 1)
+            row["effective_cpus_batch1024"] = round(cpu_ms / row["gpu_ms_per_eval_batch1024"], 1)
+        print(f"# {json.dumps(row)}", file=sys.stderr, flush=True)
+        rows.append(row)
+    result = {"metric": "time per likelihood against the number of frequency points", "unit": "ms", "n_gpus": 1,
+              "config": {"workload": "2^25-s workload injection on grids T_obs = 2^18..2^25 s, [1e-5, 0.15] Hz",
+                         "modes": len(base.modes), "sparse_knots": base.ns, "dtype": "f64"},
+              "rows": rows,
+              "context": "paper Fig. 3: one V100 against one Xeon Gold 6132 core; its plotted values are not in the text"}
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
+    if args.points_study and args.gpus == 1:
+        points_study(args)
+        return
     if args.knot_study and args.gpus == 1:
         knot_study(args)
         return
