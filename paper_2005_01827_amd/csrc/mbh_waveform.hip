@@ -137,17 +137,63 @@ __device__ double mode_time(const Source &s, int l, int m, double f)
 }
 
 // ---------------------------------------------------------------------------
-// Kernel 1: per-walker constants (one thread per walker).
+// Root brackets refined by a group of kRootLanes lanes of one wavefront.  Each
+// round places kRootLanes - 1 points evenly inside [lo, hi] (one per lane;
+// the last lane holds hi), keeps the sub-bracket in which the predicate
+// first holds, and stops once no double lies strictly inside, i.e. lo and hi
+// are adjacent doubles.  pred must be false at lo and true at hi; for a
+// predicate that switches once, the result is the smallest double at which
+// it holds, the pair that repeated halving also ends on, in about a quarter
+// of the halving rounds (each round divides the bracket by 16, not 2).  All
+// lanes of a group must call it together with the same lo and hi; the group
+// is the aligned block of kRootLanes lanes containing the caller.
+// ---------------------------------------------------------------------------
+constexpr int kRootLanes = 16;
+
+template <typename F>
+__device__ void group_bracket(double &lo, double &hi, F pred)
+{
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (kRootLanes - 1);
+    const int base = lane - gl;
+    const unsigned gmask = (1u << kRootLanes) - 1u;
+    for (int round = 0; round < 80; ++round) {
+        const double x = gl < kRootLanes - 1 ? fma(hi - lo, (double)(gl + 1) * (1.0 / kRootLanes), lo) : hi;
+        const bool inside = x > lo && x < hi;
+        const bool hit = inside && pred(x);
+        const unsigned gi = (unsigned)(__ballot(inside) >> base) & gmask;
+        const unsigned gh = (unsigned)(__ballot(hit) >> base) & gmask;
+        if (gi == 0u) break;                       // lo and hi are adjacent
+        if (gh != 0u) {
+            const int j = __ffs(gh) - 1;           // first sample where pred holds
+            const unsigned below = gi & ((1u << j) - 1u);
+            const double xj = __shfl(x, base + j);
+            const double xb = __shfl(x, base + (below ? 31 - __clz(below) : 0));
+            if (below) lo = xb;
+            hi = xj;
+        } else {
+            lo = __shfl(x, base + 31 - __clz(gi));  // pred false at every sample
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 1: per-walker constants, one group of kRootLanes lanes per walker
+// (the lanes share the root search for f_peak; lane 0 of the group writes).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(128) void k_source(const double *__restrict__ params, int B, double t0, Source *__restrict__ out)
 {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= B) return;
+    const int w = (blockIdx.x * blockDim.x + threadIdx.x) / kRootLanes;
+    const bool writer = (threadIdx.x & (kRootLanes - 1)) == 0;
+    if (w >= B) return;                            // whole groups leave together
     const double *p = params + 11 * (size_t)w;
     Source s;
     for (int i = 0; i < (int)(sizeof(Source) / sizeof(double)); ++i) reinterpret_cast<double *>(&s)[i] = 0.0;
     s.valid = params_ok(p) ? 1 : 0;
-    if (!s.valid) { out[w] = s; return; }
+    if (!s.valid) {
+        if (writer) out[w] = s;
+        return;
+    }
     const double q = p[1];
     s.M = p[0] * kMsunSec;
     s.x1 = 1.0 / (1.0 + q);
@@ -203,11 +249,7 @@ __global__ __launch_bounds__(128) void k_source(const double *__restrict__ param
     } else if (dlog_f2amp(s, hi) >= 0.0) {
         fp = hi;
     } else {
-        for (int it = 0; it < 200; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (mid <= lo || mid >= hi) break;
-            if (dlog_f2amp(s, mid) > 0.0) lo = mid; else hi = mid;
-        }
+        group_bracket(lo, hi, [&](double x) { return dlog_f2amp(s, x) <= 0.0; });
         fp = 0.5 * (lo + hi);
     }
     s.fpeak = fp;
@@ -216,7 +258,7 @@ __global__ __launch_bounds__(128) void k_source(const double *__restrict__ param
     s.al0 = a;
     s.al1 = b;
     s.A0 = sqrt(2.0 * eta / 3.0) * pow(kPi, -1.0 / 6.0) * s.M * s.M / s.Dl;
-    out[w] = s;
+    if (writer) out[w] = s;
 }
 
 // Spin-weight -2 spherical harmonic, l <= 4, via the Wigner small-d sum.
@@ -242,14 +284,14 @@ __device__ void swsh_m2(int l, int m, double th, double ph, double &re, double &
 }
 
 // ---------------------------------------------------------------------------
-// Kernel 2: frequency support and polarization weights, one thread per
-// (walker, mode).  f_start is the root of t_lm(f) = 0 by bisection to
-// adjacent doubles; f_end = min(band end, (m/2) 0.2 / M).
+// Kernel 2: frequency support and polarization weights, one group of
+// kRootLanes lanes per (walker, mode).  f_start is the root of t_lm(f) = 0,
+// bracketed to adjacent doubles; f_end = min(band end, (m/2) 0.2 / M).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_bands(int B, Modes md, GridDesc g, const Source *__restrict__ src, ModeBand *__restrict__ band)
 {
-    const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= B * md.nm) return;
+    const int id = (blockIdx.x * blockDim.x + threadIdx.x) / kRootLanes;
+    if (id >= B * md.nm) return;                   // whole groups leave together
     const int w = id / md.nm, im = id - w * md.nm;
     const int l = md.l[im], m = md.m[im];
     const Source s = src[w];
@@ -276,11 +318,7 @@ __global__ __launch_bounds__(64) void k_bands(int B, Modes md, GridDesc g, const
                 have = false;
             } else {
                 double lo = f_lo, hi = fe;
-                for (int it = 0; it < 200; ++it) {
-                    const double mid = 0.5 * (lo + hi);
-                    if (mid <= lo || mid >= hi) break;
-                    if (mode_time(s, l, m, mid) < 0.0) lo = mid; else hi = mid;
-                }
+                group_bracket(lo, hi, [&](double x) { return mode_time(s, l, m, x) >= 0.0; });
                 fs = hi;
             }
         }
@@ -306,7 +344,7 @@ __global__ __launch_bounds__(64) void k_bands(int B, Modes md, GridDesc g, const
         b.kc[0] = -0.5 * di;
         b.kc[1] = 0.5 * dr;
     }
-    band[id] = b;
+    if ((threadIdx.x & (kRootLanes - 1)) == 0) band[id] = b;
 }
 
 // ---------------------------------------------------------------------------
@@ -353,9 +391,11 @@ hipError_t launch_waveform(const double *params, int B, const Modes &md, const G
                            hipStream_t st)
 {
     if (B <= 0) return hipSuccess;
-    k_source<<<(B + 127) / 128, 128, 0, st>>>(params, B, g.t0, wk.src);
+    // kRootLanes lanes per walker and per (walker, mode)
+    constexpr int kPerBlock = 64 / kRootLanes;
+    k_source<<<(unsigned)((B + 2 * kPerBlock - 1) / (2 * kPerBlock)), 128, 0, st>>>(params, B, g.t0, wk.src);
     const int nb = B * md.nm;
-    k_bands<<<(nb + 63) / 64, 64, 0, st>>>(B, md, g, wk.src, wk.band);
+    k_bands<<<(unsigned)((nb + kPerBlock - 1) / kPerBlock), 64, 0, st>>>(B, md, g, wk.src, wk.band);
     const long long nk = (long long)nb * g.ns;
     k_knots<<<(unsigned)((nk + 255) / 256), 256, 0, st>>>(B, md, g, wk.src, wk.band, wk.kf, wk.kt, wk.fn);
     return hipGetLastError();
