@@ -124,11 +124,10 @@ __global__ void k_scan_final(const double *__restrict__ e2, int n, const double 
 // ---------------------------------------------------------------------------
 // Work items.
 // ---------------------------------------------------------------------------
-__global__ void k_walker_bands(int B, int nm, GridDesc g, const Source *__restrict__ src,
-                               const ModeBand *__restrict__ band, WalkerBand *__restrict__ wb)
+// Union band of walker w's active modes and its range of tiles.
+__device__ WalkerBand walker_band(int w, int nm, const GridDesc &g, const Source *__restrict__ src,
+                                  const ModeBand *__restrict__ band)
 {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= B) return;
     WalkerBand r;
     r.klo = 0;
     r.khi = -1;
@@ -149,7 +148,42 @@ __global__ void k_walker_bands(int B, int nm, GridDesc g, const Source *__restri
             r.ntiles = (hi - g.k0) / g.tile_bins - r.tile_lo + 1;
         }
     }
-    wb[w] = r;
+    return r;
+}
+
+__global__ void k_walker_bands(int B, int nm, GridDesc g, const Source *__restrict__ src,
+                               const ModeBand *__restrict__ band, WalkerBand *__restrict__ wb)
+{
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= B) return;
+    wb[w] = walker_band(w, nm, g, src, band);
+}
+
+// A single walker: its band, the exclusive scan over walkers, the per-tile
+// offsets, the work items (its own tiles, in order) and the zeroed counter,
+// all in one workgroup.  These are the lists the general kernels build for
+// B = 1; one launch instead of five shortens the single-walker step.
+__global__ __launch_bounds__(256) void k_items_one(int nm, GridDesc g, const Source *__restrict__ src,
+                                                   const ModeBand *__restrict__ band, WalkerBand *__restrict__ wb,
+                                                   int *__restrict__ wbase, int *__restrict__ tile_off,
+                                                   int *__restrict__ ticket, int *__restrict__ item_w,
+                                                   int *__restrict__ item_t, int max_items)
+{
+    __shared__ WalkerBand r;
+    if (threadIdx.x == 0) {
+        r = walker_band(0, nm, g, src, band);
+        wb[0] = r;
+        wbase[0] = 0;
+        wbase[1] = r.ntiles;
+        ticket[0] = 0;
+    }
+    __syncthreads();
+    const int ntiles = (g.n + g.tile_bins - 1) / g.tile_bins;
+    for (int t = threadIdx.x; t <= ntiles; t += blockDim.x) tile_off[t] = min(max(t - r.tile_lo, 0), r.ntiles);
+    for (int i = threadIdx.x; i < r.ntiles && i < max_items; i += blockDim.x) {
+        item_w[i] = 0;
+        item_t[i] = r.tile_lo + i;
+    }
 }
 
 // exclusive scan of ntiles over walkers (single block)
@@ -1060,14 +1094,21 @@ hipError_t launch_setup_data(const double *psd, const double2 *d, double *w, dou
 
 hipError_t launch_walker_bands(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st)
 {
-    if (B <= 0) return hipSuccess;
+    // a single walker's band is built with its items (launch_items), which
+    // every dense launch runs first
+    if (B <= 1) return hipSuccess;
     k_walker_bands<<<(B + 127) / 128, 128, 0, st>>>(B, md.nm, g, wk.src, wk.band, wk.wband);
     k_scan_walkers<<<1, 1024, 0, st>>>(B, wk.wband, wk.wbase);
     return hipGetLastError();
 }
 
-void launch_items(int B, const GridDesc &g, const Work &wk, int max_items, hipStream_t st)
+void launch_items(int B, int nm, const GridDesc &g, const Work &wk, int max_items, hipStream_t st)
 {
+    if (B == 1) {
+        k_items_one<<<1, 256, 0, st>>>(nm, g, wk.src, wk.band, wk.wband, wk.wbase, wk.tile_off, wk.ticket, wk.item_w,
+                                       wk.item_t, max_items);
+        return;
+    }
     const int ntiles = (g.n + g.tile_bins - 1) / g.tile_bins;
     k_tile_count<<<ntiles, 256, 0, st>>>(B, wk.wband, wk.tile_off);
     k_tile_scan<<<1, 1024, 0, st>>>(ntiles, wk.tile_off, wk.ticket);
@@ -1078,7 +1119,7 @@ hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &w
                         const Schedule &sch, bool inner, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (B <= 0) return hipSuccess;
-    launch_items(B, g, wk, max_items, st);
+    launch_items(B, md.nm, g, wk, max_items, st);
     DenseArgs a = make_args(B, md, g, wk, dt, max_items);
     a.one_per_walker = sch.one_per_walker;
     a.use_ticket = sch.one_per_walker ? 0 : 1;
@@ -1117,7 +1158,7 @@ hipError_t launch_template(const Modes &md, const GridDesc &g, const Work &wk, d
     const long long nh = 3LL * g.n;
     k_zero2<<<(unsigned)((nh + 255) / 256), 256, 0, st>>>(h, nh);
     const int max_items = (g.n + g.tile_bins - 1) / g.tile_bins + 1;
-    launch_items(1, g, wk, max_items, st);
+    launch_items(1, md.nm, g, wk, max_items, st);
     DenseArgs a = make_args(1, md, g, wk, none, max_items);
     a.h = h;
     // the same step structure as the FP64 likelihood (two bins per lane, knot
