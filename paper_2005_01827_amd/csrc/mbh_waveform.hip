@@ -143,12 +143,13 @@ __device__ double mode_time(const Source &s, int l, int m, double f)
 // first holds, and stops once no double lies strictly inside, i.e. lo and hi
 // are adjacent doubles.  pred must be false at lo and true at hi; for a
 // predicate that switches once, the result is the smallest double at which
-// it holds, the pair that repeated halving also ends on, in about a quarter
-// of the halving rounds (each round divides the bracket by 16, not 2).  All
+// it holds, the pair that repeated halving also ends on, in a fifth
+// of the halving rounds (each round divides the bracket by kRootLanes, not 2).  All
 // lanes of a group must call it together with the same lo and hi; the group
 // is the aligned block of kRootLanes lanes containing the caller.
 // ---------------------------------------------------------------------------
-constexpr int kRootLanes = 16;
+constexpr int kRootLanes = 32;
+static_assert(kRootLanes >= 2 && kRootLanes <= 32 && (kRootLanes & (kRootLanes - 1)) == 0, "group of 2..32 lanes");
 
 template <typename F>
 __device__ void group_bracket(double &lo, double &hi, F pred)
@@ -156,7 +157,7 @@ __device__ void group_bracket(double &lo, double &hi, F pred)
     const int lane = threadIdx.x & 63;
     const int gl = lane & (kRootLanes - 1);
     const int base = lane - gl;
-    const unsigned gmask = (1u << kRootLanes) - 1u;
+    const unsigned gmask = kRootLanes == 32 ? 0xffffffffu : (1u << (kRootLanes & 31)) - 1u;
     for (int round = 0; round < 80; ++round) {
         const double x = gl < kRootLanes - 1 ? fma(hi - lo, (double)(gl + 1) * (1.0 / kRootLanes), lo) : hi;
         const bool inside = x > lo && x < hi;
