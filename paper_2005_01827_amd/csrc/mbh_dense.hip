@@ -16,6 +16,7 @@
 // depend on the order or the launch shape (no floating-point atomics).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "mbh_internal.h"
@@ -1028,10 +1029,17 @@ int num_cus()
     return cus;
 }
 
-int dense_grid(int B, const Schedule &sch)
+// Workgroups of a dense launch: blocks_per_cu per compute unit, but never
+// more than the batch can have items (B walkers of at most ceil(n / tile)
+// tiles each): a workgroup past the last item would still stage the rotation
+// table and take a ticket before leaving, which for a single walker cost
+// more than its items.
+int dense_grid(int B, const GridDesc &g, const Schedule &sch)
 {
     if (sch.one_per_walker) return B;
-    return num_cus() * sch.blocks_per_cu;
+    const long long most = (long long)B * ((g.n + g.tile_bins - 1) / g.tile_bins);
+    const long long grid = (long long)num_cus() * sch.blocks_per_cu;
+    return (int)std::max(1LL, std::min(grid, most));
 }
 
 // FP32 copy of the spline coefficient table
@@ -1123,7 +1131,7 @@ hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &w
     DenseArgs a = make_args(B, md, g, wk, dt, max_items);
     a.one_per_walker = sch.one_per_walker;
     a.use_ticket = sch.one_per_walker ? 0 : 1;
-    const int grid = dense_grid(B, sch);
+    const int grid = dense_grid(B, g, sch);
     hipError_t e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     if (g.precision != 0)
@@ -1164,7 +1172,7 @@ hipError_t launch_template(const Modes &md, const GridDesc &g, const Work &wk, d
     // the same step structure as the FP64 likelihood (two bins per lane, knot
     // crossings deferred alike), so each bin's modes are summed in the same
     // order and a likelihood on this template is exactly zero at its source
-    k_dense<true, false, kBinsPerLane, false><<<dense_grid(1, Schedule()), kDenseThreads, 0, st>>>(a);
+    k_dense<true, false, kBinsPerLane, false><<<dense_grid(1, g, Schedule()), kDenseThreads, 0, st>>>(a);
     return hipGetLastError();
 }
 
