@@ -42,7 +42,7 @@ FP64_PEAK_TFLOPS = 78.6            # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 
 FLOPS_PER_MODE_BIN = 111           # 8 cubics 48, e^{i phi} 37, A e^{i phi} 2, 3 complex MACs 24
 FLOPS_PER_WALKER_BIN = 21          # per channel: d-h 2, |r|^2 w 5 (ln L needs only the residual sums)
 BYTES_PER_WALKER_BIN = 72          # d (3 x complex128) + w (3 x float64), streamed per walker
-KERNEL_REV = "dense-v21"           # traffic counters are only reused for this kernel revision
+KERNEL_REV = "dense-v22"           # traffic counters are only reused for this kernel revision
 
 
 def parse():

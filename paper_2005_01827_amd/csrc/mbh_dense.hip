@@ -645,8 +645,13 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float x)
 // the reduction from the FP64 <d|d>).
 // kROnly: accumulate only the residual sums R_c (ln L needs nothing else on
 // the FP64 path); <d|h>_c and <h|h>_c are then left at zero.
+// Occupancy: the likelihood kernel (kROnly) is held to 96 vector registers,
+// five wavefronts per SIMD, which hides more of the scalar-load waits than
+// four (measured 6 % faster; one 64-bit value is spilled, reloaded once per item);
+// six would spill 32 values and ran 27 % slower.  The other instantiations
+// keep three or four, where the tighter bound would spill more.
 template <bool kWriteH, bool kF32, int NB, bool kROnly>
-__global__ __launch_bounds__(kDenseThreads, (NB == 1 || kF32) ? 4 : 3) void k_dense(DenseArgs a)
+__global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 : 3)) void k_dense(DenseArgs a)
 {
     static_assert(!kROnly || (!kWriteH && !kF32), "residual-only sums only on the FP64 likelihood path");
     __shared__ double red[kDenseThreads / 64][kPartials];
