@@ -205,6 +205,27 @@ def test_invalid_and_empty_walkers(small, oracle):
     assert np.all(out[4, 1:] == 0.0)
 
 
+def test_invalid_and_empty_walkers_alone(small, oracle):
+    """The same edge cases one walker at a time (the single-walker item list):
+    each matches its own row of a batched call, bit for bit."""
+    import torch
+    w, psd, d, L = small
+    print("case: invalid / empty walkers, one per call", flush=True)
+    th = np.repeat(w.injection[None], 5, axis=0)
+    th[1, 1] = 1.5
+    th[2, 3] = 0.995
+    th[3, 0] = float("nan")
+    th[4, 0] = 1e9
+    batch = L.stages(th).cpu().numpy()
+    lnl_batch = L.loglike(th).cpu().numpy()
+    for i in range(len(th)):
+        one = L.stages(th[i:i + 1]).cpu().numpy()
+        assert np.array_equal(one[0], batch[i]) or (np.isneginf(one[0, 0]) and np.isneginf(batch[i, 0])), i
+        lnl = L.loglike(th[i:i + 1]).cpu().numpy()
+        assert np.array_equal(lnl, lnl_batch[i:i + 1]), i
+    torch.cuda.synchronize()
+
+
 def test_status_codes(small):
     from paper_2005_01827_amd import mbh
     w, psd, d, L = small
