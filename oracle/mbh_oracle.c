@@ -261,30 +261,41 @@ static int mode_supported(int l, int m)
            (l == 3 && m == 2) || (l == 4 && m == 3);
 }
 
-/* Leading-order post-Newtonian amplitude ratio |H_lm| / |H_22| at orbital
- * velocity v, and the constant phase arg H_lm. */
-static void mode_ratio(const Source *s, int l, int m, double v, double *ratio, double *offset)
+/* Leading-order post-Newtonian coefficient H_lm of the time-domain mode
+ * h_lm(t) ~ H_lm e^{-i m Phi(t)} of a circular binary (Phi the orbital
+ * phase), relative to H_22, at orbital velocity v: its modulus |H_lm/H_22|
+ * and its argument.  These follow from the mass quadrupole, octupole and
+ * hexadecapole (modes 22, 33, 44) and the current quadrupole, octupole and
+ * hexadecapole (21, 32, 43) of two point masses. */
+static void mode_ratio(const Source *s, int l, int m, double v, double *ratio, double *argh)
 {
     double eta = s->eta, dl = s->delta;
-    if (l == 2 && m == 2) { *ratio = 1.0; *offset = 0.0; }
-    else if (l == 3 && m == 3) { *ratio = 0.75 * sqrt(15.0 / 14.0) * dl * v; *offset = -0.5 * PI; }
-    else if (l == 4 && m == 4) { *ratio = 8.0 / 9.0 * sqrt(5.0 / 7.0) * (1.0 - 3.0 * eta) * v * v; *offset = PI; }
-    else if (l == 2 && m == 1) { *ratio = sqrt(2.0) / 3.0 * dl * v; *offset = 0.5 * PI; }
-    else if (l == 3 && m == 2) { *ratio = 1.0 / 3.0 * sqrt(5.0 / 7.0) * (1.0 - 3.0 * eta) * v * v; *offset = 0.0; }
-    else { *ratio = 9.0 / (4.0 * sqrt(70.0)) * dl * (1.0 - 2.0 * eta) * v * v * v; *offset = -0.5 * PI; }
+    if (l == 2 && m == 2) { *ratio = 1.0; *argh = 0.0; }
+    else if (l == 3 && m == 3) { *ratio = 0.75 * sqrt(15.0 / 14.0) * dl * v; *argh = -0.5 * PI; }
+    else if (l == 4 && m == 4) { *ratio = 8.0 / 9.0 * sqrt(5.0 / 7.0) * (1.0 - 3.0 * eta) * v * v; *argh = PI; }
+    else if (l == 2 && m == 1) { *ratio = dl * v / 3.0; *argh = 0.5 * PI; }
+    else if (l == 3 && m == 2) { *ratio = 1.0 / 3.0 * sqrt(5.0 / 7.0) * (1.0 - 3.0 * eta) * v * v; *argh = 0.0; }
+    else { *ratio = 9.0 / (4.0 * sqrt(70.0)) * dl * (1.0 - 2.0 * eta) * v * v * v; *argh = -0.5 * PI; }
 }
 
-/* Mode (l,m) amplitude, phase and phase derivative at frequency f: the
- * (2,2) functions at f~ = 2f/m, phase scaled by m/2. */
+/* Mode (l,m) amplitude, phase and phase derivative at frequency f > 0: the
+ * (2,2) functions at f~ = 2f/m, amplitude scaled by sqrt(2/m) |H_lm/H_22|.
+ * The frequency-domain function is the transform of h_{l,-m} = (-1)^l
+ * conj(h_lm) (the positive-frequency member of the pair, see
+ * mode_polarization).  By stationary phase, a harmonic m of the orbital
+ * phase carries the phase m Phi - 2 pi f t + pi/4 at its stationary time, so
+ * relative to (m/2) phi_22(f~) it has the constant
+ *   l pi - arg H_lm - (m - 2) pi/8
+ * (the last term is (1 - m/2) times the pi/4 of the (2,2) mode). */
 static void mode_eval(const Source *s, int l, int m, double f, double *A, double *ph, double *dph)
 {
     double ft = 2.0 * f / m;
     double v = cbrt(PI * s->M * ft);
-    double r, off, p, d1;
-    mode_ratio(s, l, m, v, &r, &off);
+    double r, argh, p, d1;
+    mode_ratio(s, l, m, v, &r, &argh);
     *A = sqrt(2.0 / m) * r * amp22(s, ft);
     phase22(s, ft, &p, &d1);
-    *ph = 0.5 * m * p + off;
+    *ph = 0.5 * m * p + (l * PI - argh - (m - 2) * PI / 8.0);
     *dph = d1;
 }
 

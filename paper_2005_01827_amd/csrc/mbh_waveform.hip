@@ -15,8 +15,9 @@
 //     from the Berti-Cardoso-Will fit form;
 //   alignment: phase and slope vanish at f_peak = argmax f^2 A_22, so
 //     t_22(f_peak) = t_coal;
-//   mode (l,m): (2,2) functions at f~ = 2f/m, phase x m/2 plus a constant,
-//     amplitude x sqrt(2/m) |H_lm/H_22| (leading post-Newtonian order).
+//   mode (l,m): (2,2) functions at f~ = 2f/m, phase x m/2 plus the constant
+//     of the stationary-phase transform, amplitude x sqrt(2/m) |H_lm/H_22|
+//     (leading post-Newtonian order of the multipole radiation).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -102,16 +103,23 @@ __device__ double dlog_f2amp(const Source &s, double f)
     return 5.0 / (6.0 * f) + kLorentzHeight * dlor / (1.0 + kLorentzHeight * lor) - tail / s.fd;
 }
 
-// |H_lm / H_22| and arg H_lm at orbital velocity v.
+// Leading-order coefficient of the time-domain mode h_lm ~ H_lm e^{-i m Phi}
+// of a circular binary relative to H_22, at orbital velocity v: r = |H_lm/H_22|
+// and the constant phase of the frequency-domain mode.  The positive
+// frequencies carry h_{l,-m} = (-1)^l conj(h_lm); stationary phase of a
+// harmonic m adds pi/4, i.e. (1 - m/2) pi/4 relative to (m/2) phi_22, so the
+// constant is l pi - arg H_lm - (m - 2) pi/8, reduced to (-pi, pi]:
+//   22: 0   33: -5pi/8 (arg H = -pi/2)   44: 3pi/4 (arg H = pi)
+//   21: -3pi/8 (arg H = pi/2)   32: pi (arg H = 0)   43: 3pi/8 (arg H = -pi/2)
 __device__ void mode_factor(const Source &s, int l, int m, double v, double &r, double &off)
 {
     const double e3 = 1.0 - 3.0 * s.eta;
     if (l == 2 && m == 2) { r = 1.0; off = 0.0; }
-    else if (l == 3 && m == 3) { r = 0.75 * sqrt(15.0 / 14.0) * s.delta * v; off = -0.5 * kPi; }
-    else if (l == 4 && m == 4) { r = (8.0 / 9.0) * sqrt(5.0 / 7.0) * e3 * v * v; off = kPi; }
-    else if (l == 2 && m == 1) { r = (sqrt(2.0) / 3.0) * s.delta * v; off = 0.5 * kPi; }
-    else if (l == 3 && m == 2) { r = (1.0 / 3.0) * sqrt(5.0 / 7.0) * e3 * v * v; off = 0.0; }
-    else { r = 9.0 / (4.0 * sqrt(70.0)) * s.delta * (1.0 - 2.0 * s.eta) * v * v * v; off = -0.5 * kPi; }
+    else if (l == 3 && m == 3) { r = 0.75 * sqrt(15.0 / 14.0) * s.delta * v; off = -0.625 * kPi; }
+    else if (l == 4 && m == 4) { r = (8.0 / 9.0) * sqrt(5.0 / 7.0) * e3 * v * v; off = 0.75 * kPi; }
+    else if (l == 2 && m == 1) { r = s.delta * v / 3.0; off = -0.375 * kPi; }
+    else if (l == 3 && m == 2) { r = (1.0 / 3.0) * sqrt(5.0 / 7.0) * e3 * v * v; off = kPi; }
+    else { r = 9.0 / (4.0 * sqrt(70.0)) * s.delta * (1.0 - 2.0 * s.eta) * v * v * v; off = 0.375 * kPi; }
 }
 
 // Mode amplitude, phase and its derivative at f (aligned (2,2) at f~ = 2f/m).
