@@ -108,18 +108,19 @@ __device__ double dlog_f2amp(const Source &s, double f)
 // and the constant phase of the frequency-domain mode.  The positive
 // frequencies carry h_{l,-m} = (-1)^l conj(h_lm); stationary phase of a
 // harmonic m adds pi/4, i.e. (1 - m/2) pi/4 relative to (m/2) phi_22, so the
-// constant is l pi - arg H_lm - (m - 2) pi/8, reduced to (-pi, pi]:
-//   22: 0   33: -5pi/8 (arg H = -pi/2)   44: 3pi/4 (arg H = pi)
-//   21: -3pi/8 (arg H = pi/2)   32: pi (arg H = 0)   43: 3pi/8 (arg H = -pi/2)
+// constant is l pi - arg H_lm - (m - 2) pi/8 (not reduced modulo 2 pi), with
+//   arg H = 0 (22, 32), -pi/2 (33, 43), pi (44), pi/2 (21).
 __device__ void mode_factor(const Source &s, int l, int m, double v, double &r, double &off)
 {
     const double e3 = 1.0 - 3.0 * s.eta;
-    if (l == 2 && m == 2) { r = 1.0; off = 0.0; }
-    else if (l == 3 && m == 3) { r = 0.75 * sqrt(15.0 / 14.0) * s.delta * v; off = -0.625 * kPi; }
-    else if (l == 4 && m == 4) { r = (8.0 / 9.0) * sqrt(5.0 / 7.0) * e3 * v * v; off = 0.75 * kPi; }
-    else if (l == 2 && m == 1) { r = s.delta * v / 3.0; off = -0.375 * kPi; }
-    else if (l == 3 && m == 2) { r = (1.0 / 3.0) * sqrt(5.0 / 7.0) * e3 * v * v; off = kPi; }
-    else { r = 9.0 / (4.0 * sqrt(70.0)) * s.delta * (1.0 - 2.0 * s.eta) * v * v * v; off = 0.375 * kPi; }
+    double argh;
+    if (l == 2 && m == 2) { r = 1.0; argh = 0.0; }
+    else if (l == 3 && m == 3) { r = 0.75 * sqrt(15.0 / 14.0) * s.delta * v; argh = -0.5 * kPi; }
+    else if (l == 4 && m == 4) { r = (8.0 / 9.0) * sqrt(5.0 / 7.0) * e3 * v * v; argh = kPi; }
+    else if (l == 2 && m == 1) { r = s.delta * v / 3.0; argh = 0.5 * kPi; }
+    else if (l == 3 && m == 2) { r = (1.0 / 3.0) * sqrt(5.0 / 7.0) * e3 * v * v; argh = 0.0; }
+    else { r = 9.0 / (4.0 * sqrt(70.0)) * s.delta * (1.0 - 2.0 * s.eta) * v * v * v; argh = -0.5 * kPi; }
+    off = l * kPi - argh - (m - 2) * kPi / 8.0;
 }
 
 // Mode amplitude, phase and its derivative at f (aligned (2,2) at f~ = 2f/m).
