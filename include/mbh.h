@@ -54,7 +54,9 @@ typedef enum {
 
 typedef enum {
     MBH_FP64 = 0,     /* whole path in double precision                     */
-    MBH_FP32C = 1     /* dense stage in float with compensated accumulation */
+    MBH_FP32C = 1     /* dense stage: FP64 phase, FP32 template, residual d - h
+                         formed and summed in float-float against the whitened
+                         data held as an FP32 pair (about 48 bits)           */
 } mbh_precision;
 
 typedef struct {
@@ -95,15 +97,17 @@ mbh_status mbh_waveform_gen(mbh_ctx *ctx, const double *params_dev, int B, void 
  * T^{A,E,T}_lm(f_j, t_lm(f_j)) at every knot, the orbital delay phase folded
  * into the phase, then not-a-knot cubic-spline coefficients of the eight
  * real functions per mode.  Requires a preceding mbh_waveform_gen with the
- * same B on the same stream. */
+ * same B on the same stream: MBH_EINVAL (nothing launched) otherwise. */
 mbh_status mbh_response(mbh_ctx *ctx, int B, void *stream);
 
 /* Sec. II.A (dense interpolation) and Eqs. NLL, innerprod, innerprodsum:
  * interpolate every mode onto the dense bins of its band, sum modes per
  * channel, and reduce, per walker, out7_dev[B][7] = {ln L, <d|h>_A, <d|h>_E,
  * <d|h>_T, <h|h>_A, <h|h>_E, <h|h>_T} (device).  The reduction is
- * deterministic (fixed order, no floating-point atomics).  Requires a
- * preceding mbh_response with the same B on the same stream. */
+ * deterministic (fixed order, no floating-point atomics).  Requires that
+ * the last call to fill the workspace was mbh_response, mbh_loglike_batch,
+ * mbh_autotune or mbh_set_sparse with the same B (or mbh_template, B = 1) on
+ * the same stream: MBH_EINVAL (nothing launched) otherwise.  B = 0 is a no-op. */
 mbh_status mbh_interp_and_inner(mbh_ctx *ctx, int B, double *out7_dev, void *stream);
 
 /* The three stages above in one call, launched as one captured HIP graph per

@@ -27,7 +27,8 @@ struct mbh_ctx {
     double2 *d = nullptr;
     double *w = nullptr;
     double *pre = nullptr;
-    float2 *dw32 = nullptr;       // FP32 dense stage only
+    float2 *dhi32 = nullptr;      // FP32 dense stage only
+    float2 *dlo32 = nullptr;
     float *sw32 = nullptr;
     // workspace
     Work wk;
@@ -37,7 +38,11 @@ struct mbh_ctx {
     std::map<int, hipGraphExec_t> graphs;   // per batch size
     hipGraph_t graph_tmp = nullptr;
     std::string err;
-    int last_B = -1;              // B of the last waveform_gen (stage checks)
+    // stage order of the staged calls: the last completed stage over the
+    // workspace (0 none, 1 waveform_gen, 2 response or a full evaluation) and
+    // the batch size it covered
+    int stage = 0;
+    int stage_B = 0;
     bool timing = false;
     Schedule sch;                 // dense launch shape (mbh_set_schedule / mbh_autotune)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -112,7 +117,23 @@ bool mode_ok(int l, int m)
            (l == 3 && m == 2) || (l == 4 && m == 3);
 }
 
-Data data_of(const mbh_ctx *c) { return Data{c->d, c->w, c->pre, c->dw32, c->sw32}; }
+Data data_of(const mbh_ctx *c) { return Data{c->d, c->w, c->pre, c->dhi32, c->dlo32, c->sw32}; }
+
+// The workspace must hold stage 'need' (or later) for exactly B walkers.
+mbh_status check_stage(mbh_ctx *c, int need, int B, const char *call)
+{
+    if (B == 0) return MBH_OK;
+    if (c->stage < need || c->stage_B != B)
+        return fail(c, MBH_EINVAL, "mbh: %s needs a preceding %s with the same B (workspace holds stage %d for B = %d)",
+                    call, need == 1 ? "mbh_waveform_gen" : "mbh_response", c->stage, c->stage_B);
+    return MBH_OK;
+}
+
+void set_stage(mbh_ctx *c, int stage, int B)
+{
+    c->stage = stage;
+    c->stage_B = B;
+}
 
 mbh_status check_B(mbh_ctx *c, int B)
 {
@@ -227,7 +248,8 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
     TRY(dalloc(c, &c->wk.cis_tab, (size_t)kCisTabDoubles));
     TRY(dalloc(c, &c->wk.cis32, (size_t)32));
     if (desc->precision == MBH_FP32C) {
-        TRY(dalloc(c, &c->dw32, (size_t)3 * n));
+        TRY(dalloc(c, &c->dhi32, (size_t)3 * n));
+        TRY(dalloc(c, &c->dlo32, (size_t)3 * n));
         TRY(dalloc(c, &c->sw32, (size_t)3 * n));
         TRY(dalloc(c, &c->wk.coef32, (size_t)B * nm * (ns - 1) * kCoefPerIv));
     }
@@ -241,8 +263,11 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
     if ((e = hipMemcpy(c->wk.cis_tab, cis_host, sizeof(double) * ncis, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->wk.cis32, cis32_host, sizeof(float) * ncis32, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d, desc->data, sizeof(double) * 6 * n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(c->wk.src, 0, sizeof(Source) * B)) != hipSuccess ||
+        (e = hipMemset(c->wk.band, 0, sizeof(ModeBand) * B * nm)) != hipSuccess ||
         (e = hipMemcpy(psd_dev, desc->psd, sizeof(double) * 3 * n, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = launch_setup_data(psd_dev, c->d, c->w, c->pre, scratch, c->dw32, c->sw32, c->g, 4.0 * desc->df, nullptr)) !=
+        (e = launch_setup_data(psd_dev, c->d, c->w, c->pre, scratch, c->dhi32, c->dlo32, c->sw32, c->g, 4.0 * desc->df,
+                           nullptr)) !=
             hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess) {
         release(c);
@@ -276,9 +301,10 @@ mbh_status mbh_waveform_gen(mbh_ctx *ctx, const double *params_dev, int B, void 
     mbh_status st = check_B(ctx, B);
     if (st) return st;
     if (B > 0 && !params_dev) return fail(ctx, MBH_EINVAL, "mbh: null params");
+    set_stage(ctx, 0, 0);
     hipError_t e = launch_waveform(params_dev, B, ctx->md, ctx->g, ctx->wk, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "waveform_gen");
-    ctx->last_B = B;
+    set_stage(ctx, 1, B);
     return MBH_OK;
 }
 
@@ -287,10 +313,12 @@ mbh_status mbh_response(mbh_ctx *ctx, int B, void *stream)
     if (!ctx) return MBH_EINVAL;
     mbh_status st = check_B(ctx, B);
     if (st) return st;
+    if ((st = check_stage(ctx, 1, B, "mbh_response"))) return st;
     hipError_t e = launch_response(B, ctx->md, ctx->g, ctx->wk, (hipStream_t)stream);
     if (e == hipSuccess) e = launch_spline(B, ctx->md, ctx->g, ctx->wk, (hipStream_t)stream);
     if (e == hipSuccess) e = launch_coef32(B, ctx->md, ctx->g, ctx->wk, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "response");
+    if (B > 0) set_stage(ctx, 2, B);
     return MBH_OK;
 }
 
@@ -300,6 +328,7 @@ mbh_status mbh_interp_and_inner(mbh_ctx *ctx, int B, double *out7_dev, void *str
     mbh_status st = check_B(ctx, B);
     if (st) return st;
     if (B > 0 && !out7_dev) return fail(ctx, MBH_EINVAL, "mbh: null out7");
+    if ((st = check_stage(ctx, 2, B, "mbh_interp_and_inner"))) return st;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_walker_bands(B, ctx->md, ctx->g, ctx->wk, s);
     if (e == hipSuccess) e = launch_dense(B, ctx->md, ctx->g, ctx->wk, data_of(ctx), ctx->max_items, ctx->sch, true, s);
@@ -315,6 +344,7 @@ mbh_status mbh_loglike_batch(mbh_ctx *ctx, const double *params_dev, int B, doub
     if (st) return st;
     if (B == 0) return MBH_OK;
     if (!params_dev || !logL_dev) return fail(ctx, MBH_EINVAL, "mbh: null params or logL");
+    set_stage(ctx, 0, 0);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(ctx->params, params_dev, sizeof(double) * 11 * B, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "params copy");
@@ -330,7 +360,7 @@ mbh_status mbh_loglike_batch(mbh_ctx *ctx, const double *params_dev, int B, doub
         if (st != MBH_OK) return st;
         e = hipMemcpyAsync(logL_dev, ctx->logL, sizeof(double) * B, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(ctx, e, "logL copy");
-        ctx->last_B = B;
+        set_stage(ctx, 2, B);
         return MBH_OK;
     }
     auto it = ctx->graphs.find(B);
@@ -362,7 +392,7 @@ mbh_status mbh_loglike_batch(mbh_ctx *ctx, const double *params_dev, int B, doub
     if ((e = hipGraphLaunch(it->second, s)) != hipSuccess) return hip_fail(ctx, e, "graph launch");
     e = hipMemcpyAsync(logL_dev, ctx->logL, sizeof(double) * B, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "logL copy");
-    ctx->last_B = B;
+    set_stage(ctx, 2, B);
     return MBH_OK;
 }
 
@@ -422,6 +452,7 @@ mbh_status mbh_autotune(mbh_ctx *ctx, const double *params_dev, int B, int reps,
     if (st) return st;
     if (!params_dev) return fail(ctx, MBH_EINVAL, "mbh: null params");
     if (reps < 1 || reps > 100) return fail(ctx, MBH_EINVAL, "mbh: reps %d outside [1, 100]", reps);
+    set_stage(ctx, 0, 0);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_waveform(params_dev, B, ctx->md, ctx->g, ctx->wk, s);
     if (e == hipSuccess) e = launch_response(B, ctx->md, ctx->g, ctx->wk, s);
@@ -463,7 +494,7 @@ mbh_status mbh_autotune(mbh_ctx *ctx, const double *params_dev, int B, int reps,
     drop_graphs(ctx);
     ctx->sch.blocks_per_cu = best;
     ctx->sch.one_per_walker = 0;
-    ctx->last_B = B;
+    set_stage(ctx, 2, B);
     if (best_bpc_host) *best_bpc_host = best;
     if (best_ms_host) *best_ms_host = best_ms;
     return MBH_OK;
@@ -473,6 +504,7 @@ mbh_status mbh_template(mbh_ctx *ctx, const double *params_dev, double *h_dev, v
 {
     if (!ctx) return MBH_EINVAL;
     if (!params_dev || !h_dev) return fail(ctx, MBH_EINVAL, "mbh: null params or h");
+    set_stage(ctx, 0, 0);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_waveform(params_dev, 1, ctx->md, ctx->g, ctx->wk, s);
     if (e == hipSuccess) e = launch_response(1, ctx->md, ctx->g, ctx->wk, s);
@@ -480,7 +512,7 @@ mbh_status mbh_template(mbh_ctx *ctx, const double *params_dev, double *h_dev, v
     if (e == hipSuccess) e = launch_walker_bands(1, ctx->md, ctx->g, ctx->wk, s);
     if (e == hipSuccess) e = launch_template(ctx->md, ctx->g, ctx->wk, reinterpret_cast<double2 *>(h_dev), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "template");
-    ctx->last_B = 1;
+    set_stage(ctx, 2, 1);
     return MBH_OK;
 }
 
@@ -578,6 +610,7 @@ mbh_status mbh_set_sparse(mbh_ctx *ctx, int B, const int64_t *band_host, const d
             mb.fe = fband_host[((size_t)w * nm + i) * 2 + 1];
         }
     }
+    set_stage(ctx, 0, 0);
     hipError_t e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = hipMemcpy(ctx->wk.src, src.data(), sizeof(Source) * B, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->wk.band, b.data(), sizeof(ModeBand) * b.size(), hipMemcpyHostToDevice);
@@ -588,7 +621,7 @@ mbh_status mbh_set_sparse(mbh_ctx *ctx, int B, const int64_t *band_host, const d
     if (e == hipSuccess) e = launch_coef32(B, ctx->md, ctx->g, ctx->wk, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(ctx, e, "set_sparse");
-    ctx->last_B = B;
+    if (B > 0) set_stage(ctx, 2, B);
     return MBH_OK;
 }
 
