@@ -15,7 +15,30 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mbh_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "libmbh_oracle.so")
+CFLAGS = ["-O3", "-march=native", "-ffp-contract=off", "-std=gnu11", "-Wall", "-fopenmp", "-fPIC", "-shared"]
+
+
+def _host_tag() -> str:
+    """Short tag of this host's CPU model and instruction-set flags: the
+    library is built with -march=native, so each kind of host builds its
+    own copy instead of loading one built for another CPU."""
+    import hashlib
+    model, flags = "", ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if not model and line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                elif not flags and line.startswith("flags"):
+                    flags = line.split(":", 1)[1].strip()
+                if model and flags:
+                    break
+    except OSError:
+        pass
+    return hashlib.sha1((model + "|" + flags).encode()).hexdigest()[:12]
+
+
+_LIB_PATH = os.path.join(_HERE, f"libmbh_oracle_{_host_tag()}.so")
 
 SUPPORTED_MODES = ((2, 2), (3, 3), (4, 4), (2, 1), (3, 2), (4, 3))
 
@@ -24,12 +47,23 @@ _ip = ctypes.POINTER(ctypes.c_int)
 _lp = ctypes.POINTER(ctypes.c_int64)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, OpenMP)."""
+    """Compile the oracle with gcc: -O3 -march=native, FMA contraction off
+    (plain IEEE double operations, no fast-math), OpenMP over walkers."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp"
-        cmd = ["gcc", "-O2", "-std=gnu11", "-Wall", "-fopenmp", "-fPIC", "-shared",
-               "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH

@@ -33,8 +33,8 @@ constexpr int kScanPer = 8;
 constexpr int kScanChunk = kScanThreads * kScanPer;
 
 __global__ void k_weights(const double *__restrict__ psd, const double2 *__restrict__ d, double *__restrict__ w,
-                          double *__restrict__ e2, float2 *__restrict__ dw32, float *__restrict__ sw32, long long total,
-                          double df4)
+                          double *__restrict__ e2, float2 *__restrict__ dhi32, float2 *__restrict__ dlo32,
+                          float *__restrict__ sw32, long long total, double df4)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
@@ -42,12 +42,16 @@ __global__ void k_weights(const double *__restrict__ psd, const double2 *__restr
     w[i] = wi;
     const double2 di = d[i];
     e2[i] = (di.x * di.x + di.y * di.y) * wi;
-    if (dw32) {
-        // whitened FP32 copies: d sqrt(w) is O(1) and sqrt(w) stays inside the
-        // FP32 range where w itself (up to ~1e44 near the arm-transfer nulls)
-        // would not
+    if (dhi32) {
+        // whitened data d sqrt(w) as an FP32 pair hi + lo (about 48 bits), so
+        // that the residual d - h of the FP32 stage is formed without the
+        // rounding of the data; sqrt(w) in FP32 stays inside the FP32 range
+        // where w itself (up to ~1e44 near the arm-transfer nulls) would not
         const double sq = sqrt(wi);
-        dw32[i] = make_float2((float)(di.x * sq), (float)(di.y * sq));
+        const double xr = di.x * sq, xi = di.y * sq;
+        const float hr = (float)xr, hi = (float)xi;
+        dhi32[i] = make_float2(hr, hi);
+        dlo32[i] = make_float2((float)(xr - (double)hr), (float)(xi - (double)hi));
         sw32[i] = (float)sq;
     }
 }
@@ -320,7 +324,8 @@ struct DenseArgs {
     double2 *h;          // template output (WriteH only)
     const double *cis_tab;
     // FP32 dense stage
-    const float2 *dw32;
+    const float2 *dhi32;
+    const float2 *dlo32;
     const float *sw32;
     const float *coef32;
     const float *cis32;
@@ -617,13 +622,39 @@ __device__ __forceinline__ void mode_bins32_u(const CisConst &K, const CisConst3
         }
 }
 
-// Kahan-compensated FP32 sum: s + c carries the running total.
+// Kahan-compensated FP32 sum: s - c carries the running total.
 __device__ __forceinline__ void kahan_add(float &s, float &c, float x)
 {
+#pragma clang fp contract(off)
     const float y = x - c;
     const float t = s + y;
     c = (t - s) - y;
     s = t;
+}
+
+// Residual square of the FP32 stage, one real component, in float-float:
+// r = (dh + dl) - ht with the data as an FP32 pair and the whitened template
+// ht in FP32.  TwoSum (Knuth) makes dh - ht exact as s + e, so r = s + rl
+// with rl = e + dl; r^2 = s^2 + 2 s rl (+ rl^2, below 2^-48 r^2), with s^2
+// split exactly by an FMA (TwoProd, Dekker / Ogita-Rump-Oishi).  The high
+// part joins the running sum (hs, ls) by TwoSum and every low part goes to
+// ls.  Contraction stays off here: fusing a product into the sums would
+// break the error-free transformations.
+__device__ __forceinline__ void ff_resid_add(float dh, float dl, float ht, float &hs, float &ls)
+{
+#pragma clang fp contract(off)
+    const float s = dh - ht;
+    const float bv = s - dh;
+    const float e = (dh - (s - bv)) + (-ht - bv);
+    const float rl = e + dl;
+    const float p = s * s;
+    const float pe = __builtin_fmaf(s, s, -p);
+    const float q = __builtin_fmaf(s + s, rl, pe);
+    const float t = hs + p;
+    const float bt = t - hs;
+    const float et = (hs - (t - bt)) + (p - bt);
+    hs = t;
+    ls = ls + (et + q);
 }
 
 // A work item is (walker, tile); each of the four wavefronts of a block takes
@@ -640,20 +671,21 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float x)
 // Only the current bin's template lives in registers; the residual sums are
 // accumulated per step.
 //
-// kF32 selects the FP32 stage: whitened FP32 data, FP32 template, and
-// Kahan-compensated FP32 sums of <d|h> and <h|h> (the residual is formed in
-// the reduction from the FP64 <d|d>).
-// kROnly: accumulate only the residual sums R_c (ln L needs nothing else on
-// the FP64 path); <d|h>_c and <h|h>_c are then left at zero.
-// Occupancy: the likelihood kernel (kROnly) is held to 96 vector registers,
-// five wavefronts per SIMD, which hides more of the scalar-load waits than
-// four (measured 6 % faster; one 64-bit value is spilled, reloaded once per item);
-// six would spill 32 values and ran 27 % slower.  The other instantiations
-// keep three or four, where the tighter bound would spill more.
+// kF32 selects the FP32 stage: FP64 phase, FP32 template, whitened data as
+// an FP32 pair, and the residual sums R_c in float-float (ff_resid_add), so
+// that ln L keeps the residual form of Eq. NLL and only the template carries
+// FP32 rounding; <d|h> and <h|h> (inner-product kernel only) are Kahan sums.
+// kROnly: accumulate only the residual sums R_c (ln L needs nothing else);
+// <d|h>_c and <h|h>_c are then left at zero.
+// Occupancy: the FP64 likelihood kernel (kROnly) is held to 96 vector
+// registers, five wavefronts per SIMD, which hides more of the scalar-load
+// waits than four (measured 6 % faster; one 64-bit value is spilled, reloaded
+// once per item); six would spill 32 values and ran 27 % slower.  The other
+// instantiations keep three or four, where the tighter bound would spill more.
 template <bool kWriteH, bool kF32, int NB, bool kROnly>
 __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 : 3)) void k_dense(DenseArgs a)
 {
-    static_assert(!kROnly || (!kWriteH && !kF32), "residual-only sums only on the FP64 likelihood path");
+    static_assert(!kROnly || !kWriteH, "residual-only sums only on the likelihood paths");
     __shared__ double red[kDenseThreads / 64][kPartials];
     __shared__ double2 rot[kRotN];
     __shared__ int xcur[kDenseThreads / 64][kMaxModes];   // interval of a deferred mode, per wavefront
@@ -726,7 +758,10 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
         double acc[kPartials];
 #pragma unroll
         for (int q = 0; q < kPartials; ++q) acc[q] = 0.0;
+        float rh[3], rl[3];   // FP32 stage: float-float residual sums R_c
         float ks[6], kc[6];   // FP32 stage: Kahan sums of DH_c, HH_c
+#pragma unroll
+        for (int q = 0; q < 3; ++q) rh[q] = rl[q] = 0.0f;
 #pragma unroll
         for (int q = 0; q < 6; ++q) ks[q] = kc[q] = 0.0f;
 
@@ -738,23 +773,12 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
             double f[NB];
             double2 dv[NB][3];
             double wv[NB][3];
-            float2 dv32[NB][3];
-            float sv32[NB][3];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 k[b] = s0 + 64 * b + lane;
                 inw[b] = (k[b] >= wb.klo) && (k[b] <= wb.khi);
                 idx[b] = inw[b] ? k[b] - a.k0 : 0;
                 f[b] = (double)k[b] * a.df;
-            }
-            if (!kWriteH && kF32) {
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-#pragma unroll
-                    for (int ch = 0; ch < 3; ++ch) {
-                        dv32[b][ch] = a.dw32[(size_t)ch * a.n + idx[b]];
-                        sv32[b][ch] = a.sw32[(size_t)ch * a.n + idx[b]];
-                    }
             }
             unsigned xmask = 0u;   // modes whose step crosses a knot (wave-uniform)
             double hr[NB][3], hi[NB][3];
@@ -855,19 +879,23 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
                         for (int ch = 0; ch < 3; ++ch)
                             a.h[(size_t)ch * a.n + idx[b]] = make_double2(hr[b][ch], hi[b][ch]);
             } else if (kF32) {
+                // the data are loaded after the modes, as on the FP64 path
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     if (!inw[b]) continue;
 #pragma unroll
                     for (int ch = 0; ch < 3; ++ch) {
-                        // whitened template h sqrt(w); <d|h> and <h|h> are summed
-                        // here and the residual is formed in the reduction with
-                        // the FP64 <d|d> (summing the residual directly in FP32
-                        // was measured to be less accurate: the FP32 whitened
-                        // data then add an error floor of ~1e-4 per walker)
-                        const float wr = hr32[b][ch] * sv32[b][ch], wi = hi32[b][ch] * sv32[b][ch];
-                        kahan_add(ks[ch], kc[ch], fmaf(dv32[b][ch].x, wr, dv32[b][ch].y * wi));
-                        kahan_add(ks[3 + ch], kc[3 + ch], fmaf(wr, wr, wi * wi));
+                        const size_t o = (size_t)ch * a.n + idx[b];
+                        const float2 dh = a.dhi32[o], dl = a.dlo32[o];
+                        const float sw = a.sw32[o];
+                        // whitened template h sqrt(w)
+                        const float wr = hr32[b][ch] * sw, wi = hi32[b][ch] * sw;
+                        ff_resid_add(dh.x, dl.x, wr, rh[ch], rl[ch]);
+                        ff_resid_add(dh.y, dl.y, wi, rh[ch], rl[ch]);
+                        if (!kROnly) {
+                            kahan_add(ks[ch], kc[ch], fmaf(dh.x, wr, dh.y * wi));
+                            kahan_add(ks[3 + ch], kc[3 + ch], fmaf(wr, wr, wi * wi));
+                        }
                     }
                 }
             } else {
@@ -903,7 +931,10 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
         }
         if (kF32) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) acc[3 + q] = (double)ks[q] - (double)kc[q];
+            for (int q = 0; q < 3; ++q) acc[q] = (double)rh[q] + (double)rl[q];
+            if (!kROnly)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) acc[3 + q] = (double)ks[q] - (double)kc[q];
         }
 
         // wavefront butterfly, then the four wavefronts in order
@@ -956,26 +987,15 @@ __global__ void k_reduce(int B, GridDesc g, const Source *__restrict__ src, cons
         for (int q = 1; q < 7; ++q) o[q] = 0.0;
     } else {
         const WalkerBand wb = wband[w];
-        if (g.precision == 0) {
-            // residual form over the band, data-only sum outside it
-            double dd_out = 0.0;
-            for (int c = 0; c < 3; ++c) {
-                const double *p = pre + (size_t)c * (g.n + 1);
-                if (wb.ntiles > 0) dd_out += p[wb.klo - g.k0] + (p[g.n] - p[wb.khi - g.k0 + 1]);
-                else dd_out += p[g.n];
-            }
-            o[0] = -0.5 * (acc[0] + acc[1] + acc[2] + dd_out);
-        } else {
-            // FP32 stage: <d|d> in FP64 from the prefix sums, <d|h> and <h|h>
-            // from the compensated FP32 sums
-            double dd = 0.0, dh = 0.0, hh = 0.0;
-            for (int c = 0; c < 3; ++c) {
-                dd += pre[(size_t)c * (g.n + 1) + g.n];
-                dh += acc[3 + c];
-                hh += acc[6 + c];
-            }
-            o[0] = -0.5 * (dd + hh - 2.0 * dh);
+        // residual form over the band (both precisions), data-only sum
+        // outside it
+        double dd_out = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double *p = pre + (size_t)c * (g.n + 1);
+            if (wb.ntiles > 0) dd_out += p[wb.klo - g.k0] + (p[g.n] - p[wb.khi - g.k0 + 1]);
+            else dd_out += p[g.n];
         }
+        o[0] = -0.5 * (acc[0] + acc[1] + acc[2] + dd_out);
         for (int c = 0; c < 3; ++c) {
             o[1 + c] = acc[3 + c];
             o[4 + c] = acc[6 + c];
@@ -1014,7 +1034,8 @@ DenseArgs make_args(int B, const Modes &md, const GridDesc &g, const Work &wk, c
     a.partial = wk.partial;
     a.h = nullptr;
     a.cis_tab = wk.cis_tab;
-    a.dw32 = dt.dw32;
+    a.dhi32 = dt.dhi32;
+    a.dlo32 = dt.dlo32;
     a.sw32 = dt.sw32;
     a.coef32 = wk.coef32;
     a.cis32 = wk.cis32;
@@ -1092,13 +1113,14 @@ hipError_t launch_coef32(int B, const Modes &md, const GridDesc &g, const Work &
 }
 
 hipError_t launch_setup_data(const double *psd, const double2 *d, double *w, double *pre, double *scratch,
-                             float2 *dw32, float *sw32, const GridDesc &g, double df4, hipStream_t st)
+                             float2 *dhi32, float2 *dlo32, float *sw32, const GridDesc &g, double df4,
+                             hipStream_t st)
 {
     const long long total = 3LL * g.n;
     double *e2 = scratch;                  // [3][n]
     const int nchunks = (g.n + kScanChunk - 1) / kScanChunk;
     double *chunk = scratch + total;       // [3][nchunks]
-    k_weights<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(psd, d, w, e2, dw32, sw32, total, df4);
+    k_weights<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(psd, d, w, e2, dhi32, dlo32, sw32, total, df4);
     k_scan_chunks<<<dim3(nchunks, 3), kScanThreads, 0, st>>>(e2, g.n, chunk, nchunks);
     k_scan_offsets<<<3, kScanThreads, 0, st>>>(chunk, nchunks);
     k_scan_final<<<dim3(nchunks, 3), kScanThreads, 0, st>>>(e2, g.n, chunk, nchunks, pre);
@@ -1139,8 +1161,10 @@ hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &w
     const int grid = dense_grid(B, g, sch);
     hipError_t e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
-    if (g.precision != 0)
+    if (g.precision != 0 && inner)
         k_dense<false, true, kBinsPerLane, false><<<grid, kDenseThreads, 0, st>>>(a);
+    else if (g.precision != 0)
+        k_dense<false, true, kBinsPerLane, true><<<grid, kDenseThreads, 0, st>>>(a);
     else if (inner)
         k_dense<false, false, kBinsPerLane, false><<<grid, kDenseThreads, 0, st>>>(a);
     else
@@ -1167,7 +1191,7 @@ __global__ void k_zero2(double2 *__restrict__ h, long long count)
 
 hipError_t launch_template(const Modes &md, const GridDesc &g, const Work &wk, double2 *h, hipStream_t st)
 {
-    Data none = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    Data none = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     const long long nh = 3LL * g.n;
     k_zero2<<<(unsigned)((nh + 255) / 256), 256, 0, st>>>(h, nh);
     const int max_items = (g.n + g.tile_bins - 1) / g.tile_bins + 1;

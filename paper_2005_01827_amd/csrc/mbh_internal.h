@@ -114,7 +114,8 @@ struct Data {
     const double2 *d;       // [3][n]   A, E, T data
     const double *w;        // [3][n]   4 df / S_n
     const double *pre;      // [3][n+1] prefix sums of |d|^2 w
-    const float2 *dw32;     // [3][n]   d sqrt(w) in FP32 (FP32 dense stage)
+    const float2 *dhi32;    // [3][n]   d sqrt(w), FP32 high part (FP32 dense stage)
+    const float2 *dlo32;    // [3][n]   d sqrt(w) - dhi32, FP32 low part
     const float *sw32;      // [3][n]   sqrt(w) in FP32
 };
 
@@ -124,9 +125,10 @@ struct Data {
 const double *cis_table_host(int *n);
 const float *cis32_table_host(int *n);
 
-// dw32 / sw32 may be null (FP64 contexts)
+// dhi32 / dlo32 / sw32 may be null (FP64 contexts)
 hipError_t launch_setup_data(const double *psd, const double2 *d, double *w, double *pre, double *scratch,
-                             float2 *dw32, float *sw32, const GridDesc &g, double df4, hipStream_t st);
+                             float2 *dhi32, float2 *dlo32, float *sw32, const GridDesc &g, double df4,
+                             hipStream_t st);
 
 // FP32 copy of the spline coefficients for the FP32 dense stage
 hipError_t launch_coef32(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st);
