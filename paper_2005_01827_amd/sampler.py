@@ -590,6 +590,18 @@ def gpu_loglike(L):
     return f
 
 
+def gpu_loglike_lisa(L, t0):
+    """ln L of LISA-frame sampling coordinates (lisaframe.to_sampling_lisa):
+    converted to SSB parameters on the host before the waveform, as the
+    sampler of Sec. II does, then evaluated through an mbh.Likelihood."""
+    from . import lisaframe
+
+    def f(x):
+        out = L.loglike(lisaframe.sampling_lisa_to_ssb(np.asarray(x), t0))
+        return out.cpu().numpy()
+    return f
+
+
 # ---------------------------------------------------------------------------
 # ESS per second: stretch only against stretch + learned proposal
 # ---------------------------------------------------------------------------

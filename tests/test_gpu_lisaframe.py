@@ -1,0 +1,59 @@
+"""Sampling in the LISA frame through the HIP likelihood (Sec. II: the
+sampler moves lambda, beta, psi, t_ref in the LISA frame and converts them to
+the SSB frame before each waveform; Sec. III.B: 4 walkers per temperature at
+each of the eight sky modes)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2005_01827_amd import inputs
+from paper_2005_01827_amd import lisaframe as LF
+from paper_2005_01827_amd import sampler as S
+
+pytestmark = pytest.mark.gpu
+
+
+def test_lisa_frame_sampling_from_the_eight_sky_modes(oracle):
+    import torch
+    from paper_2005_01827_amd import mbh
+    print("case: LISA-frame PT from the eight sky modes, small grid", flush=True)
+    w = inputs.small_config(1, seed=7)
+    g = w.grid
+    psd = inputs.psd_aet(g.freqs)
+    d = oracle.template(w.injection, g, w.modes, w.ns, w.t0) + inputs.noise(g, psd, 61)
+    nt, per_mode = 4, 4
+    L = mbh.Likelihood(g, d, psd, w.modes, w.ns, w.t0, max_batch=nt * 8 * per_mode)
+    try:
+        ll_ssb = L.loglike(w.injection[None]).cpu().numpy()[0]
+        ll_lisa = S.gpu_loglike_lisa(L, w.t0)
+        thL = LF.physical_to_lisa(w.injection, w.t0)
+        x_inj = LF.to_sampling_lisa(thL)
+        # the conversion before the waveform reproduces the SSB evaluation
+        got = ll_lisa(x_inj[None])[0]
+        print(f"[lisa] lnL at the injection: SSB {ll_ssb:.10f}  via LISA frame {got:.10f}", flush=True)
+        assert abs(got - ll_ssb) <= 1e-10 * max(abs(ll_ssb), 1.0)
+        # the true mode is the best of the eight for this loud source
+        modes = LF.sky_modes(thL)
+        ll_modes = ll_lisa(LF.to_sampling_lisa(modes))
+        print(f"[lisa] lnL at the eight sky modes - injection: {np.round(ll_modes - ll_ssb, 1)}", flush=True)
+        assert np.argmax(ll_modes) == 0
+        # parallel tempering started on the eight modes (a = 1.15, the
+        # paper's ladder cut to 4 rungs), the prior carried to the frame
+        x0 = LF.sky_mode_walkers(thL, nt, per_mode, 1e-7, 62)
+        smp = S.PTSampler(ll_lisa, LF.lisa_logprior(w.t0), S.ladder(nt), 8 * per_mode, 11, a=1.15, seed=63)
+        smp.initialize(x0)
+        assert np.all(np.isfinite(smp.state.logl))
+        smp.run(300)
+        torch.cuda.synchronize()
+    finally:
+        L.close()
+    st = smp.state
+    acc = st.accepted / np.maximum(1, st.proposed)
+    best = st.logl[0].max()
+    quad = np.mod(np.round((st.x[0, :, 7] - thL[7]) / (0.5 * math.pi)), 4)
+    print(f"[lisa] after 300 steps: best T=1 lnL - injection {best - ll_ssb:.2f}; acceptance {np.round(acc, 3)}; "
+          f"T=1 walkers per longitude mode {np.bincount(quad.astype(int), minlength=4)}", flush=True)
+    assert np.all(np.isfinite(st.logl[0]))
+    assert np.all(acc > 0.0)
+    assert best > ll_ssb - 20.0
