@@ -21,13 +21,18 @@ def test_lisa_frame_sampling_from_the_eight_sky_modes(oracle):
     w = inputs.small_config(1, seed=7)
     g = w.grid
     psd = inputs.psd_aet(g.freqs)
-    d = oracle.template(w.injection, g, w.modes, w.ns, w.t0) + inputs.noise(g, psd, 61)
+    # the Table I prior holds in the SSB frame (t_ref >= 1 s), and a sky mode
+    # moves the SSB arrival time by up to two light-travel times of 1 AU, so
+    # the source merges 2000 s after t0: every mode then lies inside the prior
+    inj = w.injection.copy()
+    inj[10] = 2000.0
+    d = oracle.template(inj, g, w.modes, w.ns, w.t0) + inputs.noise(g, psd, 61)
     nt, per_mode = 4, 4
     L = mbh.Likelihood(g, d, psd, w.modes, w.ns, w.t0, max_batch=nt * 8 * per_mode)
     try:
-        ll_ssb = L.loglike(w.injection[None]).cpu().numpy()[0]
+        ll_ssb = L.loglike(inj[None]).cpu().numpy()[0]
         ll_lisa = S.gpu_loglike_lisa(L, w.t0)
-        thL = LF.physical_to_lisa(w.injection, w.t0)
+        thL = LF.physical_to_lisa(inj, w.t0)
         x_inj = LF.to_sampling_lisa(thL)
         # the conversion before the waveform reproduces the SSB evaluation
         got = ll_lisa(x_inj[None])[0]

@@ -171,3 +171,22 @@ def test_lisa_prior_carries_the_table_one_prior():
     bad = x.copy()
     bad[:, 9] = math.pi + 0.1
     assert np.all(np.isneginf(LF.lisa_logprior(T0)(bad)))
+
+
+def test_sky_modes_inside_the_prior_when_the_merger_is_late_enough():
+    """The prior is the SSB one carried over, and a sky mode moves the SSB
+    arrival time by at most 2 AU/c (about 998 s): with t_ref = 2000 s every
+    mode has a finite prior; with t_ref = 50.25 s (Binary 1) the modes whose
+    SSB time falls below 1 s carry none."""
+    au_s = LF.AU_M / LF.C_SI
+    for tref, all_inside in ((2000.0, True), (50.25, False)):
+        th = inputs.year_grid(1).injection.copy()
+        th[10] = tref
+        thL = LF.physical_to_lisa(th, T0)
+        m = LF.sky_modes(thL)
+        t_ssb = LF.lisa_to_physical(m, T0)[:, 10]
+        assert np.all(np.abs(t_ssb - tref) <= 2.0 * au_s + 1.0)
+        lp = LF.lisa_logprior(T0)(LF.to_sampling_lisa(m))
+        assert np.isfinite(lp[0])
+        assert np.array_equal(np.isfinite(lp), t_ssb >= 1.0)
+        assert np.all(np.isfinite(lp)) == all_inside
