@@ -117,6 +117,27 @@ mbh_status mbh_interp_and_inner(mbh_ctx *ctx, int B, double *out7_dev, void *str
  * returns. */
 mbh_status mbh_loglike_batch(mbh_ctx *ctx, const double *params_dev, int B, double *logL_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * stages and kernels as mbh_loglike_batch, launched directly on 'stream'
+ * (no graph, no events), with every per-call workspace (sparse stage, spline
+ * coefficients, work-item lists, counters, partial sums) taken from one
+ * fixed 64 MiB device array per GPU that the library holds until the
+ * process ends, instead of the context's workspace.  The call allocates and
+ * frees nothing.  params_dev[B][11] and logL_dev[B] are device buffers of
+ * the caller; ln L is bitwise the value mbh_loglike_batch returns.
+ * Limits: B <= max_batch, and the workspace of B walkers (about 0.55 MB per
+ * walker with 6 modes, 256 knots and the 2^25-s grid, so about 100 walkers;
+ * more for fewer modes, knots or bins) must fit in 64 MiB: MBH_EBATCH with
+ * the required size in mbh_last_error otherwise.  MBH_EINVAL if the
+ * context's device is not the current one; MBH_EHIP if the array's device
+ * address could not be taken when the context was created.
+ * All calls on one GPU share the array, whatever their context: calls
+ * that overlap in time on one GPU (two streams, two host threads) race and
+ * give wrong results; serialize them.  The array keeps the last call's
+ * contents; the call writes every value before reading it. */
+mbh_status mbh_loglike_batch_noalloc(mbh_ctx *ctx, const double *params_dev, int B, double *logL_dev, void *stream);
+
 /* Dense template of one walker on the context's grid, h_dev[3][n][2]
  * (device, complex128 interleaved), built by the same kernels as the
  * likelihood.  Used to synthesise injections on the device. */

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,14 @@
 #include "mbh_internal.h"
 
 using namespace mbh;
+
+// Workspace of mbh_loglike_batch_noalloc, for callers that cannot allocate
+// device memory: one fixed array per GPU, held until the process ends.  Its
+// device address is taken once per device with hipGetSymbolAddress (in host
+// code the name 'scratch' is not a device address) and only that address is
+// passed to kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 struct mbh_ctx {
     mbh_ctx_desc desc;
@@ -45,6 +54,9 @@ struct mbh_ctx {
     int stage_B = 0;
     bool timing = false;
     Schedule sch;                 // dense launch shape (mbh_set_schedule / mbh_autotune)
+    int device = 0;               // device the context was created on
+    unsigned char *scratch_dev = nullptr;   // that device's copy of 'scratch' (null if unavailable)
+    std::string scratch_err;      // why scratch_dev is null
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
 };
 
@@ -156,6 +168,72 @@ mbh_status enqueue_all(mbh_ctx *c, const double *params, int B, double *out7, do
         return hip_fail(c, e, "dense");
     if ((e = launch_reduce(B, c->g, c->wk, data_of(c), out7, logL, st)) != hipSuccess) return hip_fail(c, e, "reduce");
     return MBH_OK;
+}
+
+// Device address of 'scratch' on each device, taken once per device with
+// that device current.
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch_addr;
+
+// Sets c->scratch_dev for the current device (c->scratch_err on failure).
+void bind_scratch(mbh_ctx *c)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        c->scratch_err = std::string("hipGetDevice failed: ") + hipGetErrorString(e);
+        return;
+    }
+    auto it = g_scratch_addr.find(c->device);
+    if (it == g_scratch_addr.end()) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            c->scratch_err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+            return;
+        }
+        it = g_scratch_addr.emplace(c->device, static_cast<unsigned char *>(p)).first;
+    }
+    c->scratch_dev = it->second;
+}
+
+// Per-call workspace of B walkers carved from base (256-byte aligned
+// pieces); returns the bytes it needs.  base == nullptr only measures.
+// The read-only sin/cos tables stay the context's.
+size_t carve_workspace(const mbh_ctx *c, int B, unsigned char *base, Work *wk, int *max_items)
+{
+    const int nm = c->md.nm, ns = c->g.ns;
+    const long long ntile_max = (c->g.n + c->g.tile_bins - 1) / c->g.tile_bins + 1;
+    const long long items = (long long)B * ntile_max;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        void *p = base ? static_cast<void *>(base + off) : nullptr;
+        off += (std::max<size_t>(bytes, 1) + 255) & ~size_t(255);
+        return p;
+    };
+    Work w = {};
+    w.src = static_cast<Source *>(take(sizeof(Source) * B));
+    w.band = static_cast<ModeBand *>(take(sizeof(ModeBand) * B * nm));
+    w.wband = static_cast<WalkerBand *>(take(sizeof(WalkerBand) * B));
+    w.kf = static_cast<double *>(take(sizeof(double) * B * nm * ns));
+    w.kt = static_cast<double *>(take(sizeof(double) * B * nm * ns));
+    w.fn = static_cast<double *>(take(sizeof(double) * B * nm * kNumFn * ns));
+    w.coef = static_cast<double *>(take(sizeof(double) * B * nm * (ns - 1) * kCoefPerIv));
+    w.kbin = static_cast<int *>(take(sizeof(int) * B * nm * ns));
+    w.item_w = static_cast<int *>(take(sizeof(int) * items));
+    w.item_t = static_cast<int *>(take(sizeof(int) * items));
+    w.tile_off = static_cast<int *>(take(sizeof(int) * (ntile_max + 1)));
+    w.ticket = static_cast<int *>(take(sizeof(int) * 64));
+    w.wbase = static_cast<int *>(take(sizeof(int) * (B + 1)));
+    w.partial = static_cast<double *>(take(sizeof(double) * items * kPartials));
+    w.out7 = nullptr;
+    if (c->precision == MBH_FP32C) w.coef32 = static_cast<float *>(take(sizeof(float) * B * nm * (ns - 1) * kCoefPerIv));
+    w.cis_tab = c->wk.cis_tab;
+    w.cis32 = c->wk.cis32;
+    if (wk) *wk = w;
+    if (max_items) *max_items = (int)std::min<long long>(items, 0x7fffffffLL);
+    return off;
 }
 
 }  // namespace
@@ -283,6 +361,7 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
             ++it;
         }
     }
+    bind_scratch(c);
     *out = c;
     return MBH_OK;
 }
@@ -393,6 +472,44 @@ mbh_status mbh_loglike_batch(mbh_ctx *ctx, const double *params_dev, int B, doub
     e = hipMemcpyAsync(logL_dev, ctx->logL, sizeof(double) * B, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "logL copy");
     set_stage(ctx, 2, B);
+    return MBH_OK;
+}
+
+mbh_status mbh_loglike_batch_noalloc(mbh_ctx *ctx, const double *params_dev, int B, double *logL_dev, void *stream)
+{
+    if (!ctx) return MBH_EINVAL;
+    mbh_status st = check_B(ctx, B);
+    if (st) return st;
+    if (B == 0) return MBH_OK;
+    if (!params_dev || !logL_dev) return fail(ctx, MBH_EINVAL, "mbh: null params or logL");
+    if (!ctx->scratch_dev) return fail(ctx, MBH_EHIP, "mbh: no static workspace on this device (%s)", ctx->scratch_err.c_str());
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipGetDevice");
+    if (dev != ctx->device)
+        return fail(ctx, MBH_EINVAL, "mbh: context belongs to device %d but device %d is current", ctx->device, dev);
+    const size_t need = carve_workspace(ctx, B, nullptr, nullptr, nullptr);
+    if (need > kScratchBytes)
+        return fail(ctx, MBH_EBATCH,
+                    "mbh: B = %d needs %zu bytes of workspace, more than the %zu-byte static workspace of "
+                    "mbh_loglike_batch_noalloc (use a smaller batch or mbh_loglike_batch)",
+                    B, need, kScratchBytes);
+    Work wk;
+    int max_items = 0;
+    carve_workspace(ctx, B, ctx->scratch_dev, &wk, &max_items);
+    // the same kernels in the same order as the graph of mbh_loglike_batch;
+    // every scratch value is written before it is read (the tile list
+    // kernels reset the work-item counter), so nothing is cleared here
+    hipStream_t s = (hipStream_t)stream;
+    const Data dt = data_of(ctx);
+    if ((e = launch_waveform(params_dev, B, ctx->md, ctx->g, wk, s)) != hipSuccess) return hip_fail(ctx, e, "waveform");
+    if ((e = launch_response(B, ctx->md, ctx->g, wk, s)) != hipSuccess) return hip_fail(ctx, e, "response");
+    if ((e = launch_spline(B, ctx->md, ctx->g, wk, s)) != hipSuccess) return hip_fail(ctx, e, "spline");
+    if ((e = launch_coef32(B, ctx->md, ctx->g, wk, s)) != hipSuccess) return hip_fail(ctx, e, "coef32");
+    if ((e = launch_walker_bands(B, ctx->md, ctx->g, wk, s)) != hipSuccess) return hip_fail(ctx, e, "bands");
+    if ((e = launch_dense(B, ctx->md, ctx->g, wk, dt, max_items, ctx->sch, false, s)) != hipSuccess)
+        return hip_fail(ctx, e, "dense");
+    if ((e = launch_reduce(B, ctx->g, wk, dt, nullptr, logL_dev, s)) != hipSuccess) return hip_fail(ctx, e, "reduce");
     return MBH_OK;
 }
 

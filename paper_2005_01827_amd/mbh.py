@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "MBH_OK", -1: "MBH_EINVAL", -2: "MBH_ENOMEM", -3: "MBH_EHIP",
 
 # Every entry point declared in include/mbh.h.
 EXPORTED = ("mbh_ctx_create", "mbh_ctx_destroy", "mbh_last_error", "mbh_waveform_gen", "mbh_response",
-            "mbh_interp_and_inner", "mbh_loglike_batch", "mbh_template", "mbh_get_sparse", "mbh_set_sparse",
+            "mbh_interp_and_inner", "mbh_loglike_batch", "mbh_loglike_batch_noalloc", "mbh_template", "mbh_get_sparse", "mbh_set_sparse",
             "mbh_set_timing", "mbh_get_timing", "mbh_set_schedule", "mbh_get_schedule", "mbh_autotune",
             "mbh_flow_create", "mbh_flow_destroy", "mbh_flow_last_error",
             "mbh_flow_num_params", "mbh_flow_get_layout", "mbh_flow_get_params", "mbh_flow_set_params",
@@ -62,10 +62,12 @@ def load_library(path: str = LIB_PATH):
     L.mbh_response.argtypes = [vp, ctypes.c_int, vp]
     L.mbh_interp_and_inner.argtypes = [vp, ctypes.c_int, vp, vp]
     L.mbh_loglike_batch.argtypes = [vp, vp, ctypes.c_int, vp, vp]
+    L.mbh_loglike_batch_noalloc.argtypes = [vp, vp, ctypes.c_int, vp, vp]
     L.mbh_template.argtypes = [vp, vp, vp, vp]
     L.mbh_get_sparse.argtypes = [vp, ctypes.c_int, i64p, dp, dp, dp, dp, vp]
     L.mbh_set_sparse.argtypes = [vp, ctypes.c_int, i64p, dp, dp, dp, vp]
-    for name in ("mbh_waveform_gen", "mbh_response", "mbh_interp_and_inner", "mbh_loglike_batch", "mbh_template",
+    for name in ("mbh_waveform_gen", "mbh_response", "mbh_interp_and_inner", "mbh_loglike_batch",
+                 "mbh_loglike_batch_noalloc", "mbh_template",
                  "mbh_get_sparse", "mbh_set_sparse"):
         getattr(L, name).restype = ctypes.c_int
     L.mbh_set_timing.argtypes = [vp, ctypes.c_int]
@@ -201,6 +203,22 @@ class Likelihood:
                                                ctypes.c_void_p(out.data_ptr()), self._stream(stream)),
                     "mbh_loglike_batch")
         self._keep = p
+        return out
+
+    def loglike_noalloc(self, params, out, stream=None):
+        """ln L [B] into the caller's device tensor 'out' through the entry
+        point that allocates nothing (fixed per-GPU workspace); params must
+        already be a contiguous float64 [B][11] device tensor."""
+        t = self._torch
+        if not (isinstance(params, t.Tensor) and params.is_cuda and params.dtype == t.float64 and
+                params.dim() == 2 and params.shape[1] == 11 and params.is_contiguous()):
+            raise ValueError("params must be a contiguous float64 [B][11] device tensor")
+        B = params.shape[0]
+        if not (isinstance(out, t.Tensor) and out.is_cuda and out.dtype == t.float64 and out.numel() >= B):
+            raise ValueError("out must be a float64 device tensor of at least B entries")
+        self._check(self.lib.mbh_loglike_batch_noalloc(self.ctx, ctypes.c_void_p(params.data_ptr()), B,
+                                                       ctypes.c_void_p(out.data_ptr()), self._stream(stream)),
+                    "mbh_loglike_batch_noalloc")
         return out
 
     def template(self, params, stream=None):
