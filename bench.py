@@ -39,10 +39,24 @@ sys.path.insert(0, ROOT)
 METRIC = "loglike evals/sec (1024 walkers, 1-yr grid) + %HBM peak; ESS/sec flow vs plain"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6            # 256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
-FLOPS_PER_MODE_BIN = 111           # 8 cubics 48, e^{i phi} 37, A e^{i phi} 2, 3 complex MACs 24
-FLOPS_PER_WALKER_BIN = 21          # per channel: d-h 2, |r|^2 w 5 (ln L needs only the residual sums)
-BYTES_PER_WALKER_BIN = 72          # d (3 x complex128) + w (3 x float64), streamed per walker
-KERNEL_REV = "dense-v22"           # traffic counters are only reused for this kernel revision
+# Flops the dense kernel executes per mode-bin: 8 cubics by Horner 48;
+# e^{i phi} 21 (rounding to a 1024-entry rotation table 3, the two-part
+# remainder 4, sin to r^3 and cos to r^4 7, the table rotation 7); A e^{i phi}
+# 2; three complex multiply-accumulates 24.  Per walker-bin, per channel:
+# d - h 2, |r|^2 3, times w and accumulate 2.
+FLOPS_PER_MODE_BIN = 95
+FLOPS_PER_WALKER_BIN = 21
+# The same work as FP64 lane instructions (an FMA is one): 51 per mode-bin
+# and 15 per walker-bin; the FP64 VALU issues 256 CU x 4 SIMD x 16 lanes per
+# cycle at 2.4 GHz, 3.93e13 lane instructions per second.
+LANE_OPS_PER_MODE_BIN = 51
+LANE_OPS_PER_WALKER_BIN = 15
+LANE_OPS_PEAK = 3.93216e13
+# Relative rms template error of the FP32C dense stage: 29 FP32 roundings per
+# bin (the kernel's arithmetic), each uniform within one unit roundoff.
+SIG_REL_FP32C = 2.0 ** -24 * math.sqrt(29.0 / 3.0)
+BYTES_PER_WALKER_BIN = 72          # d (3 x complex128) + w (3 x float64), read once per walker
+KERNEL_REV = "dense-v23"           # traffic counters are only reused for this kernel revision
 
 
 def parse():
@@ -56,7 +70,18 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--cpu-threads", type=int, default=0,
-                    help="threads for the oracle baseline (default: up to 16 host cores)")
+                    help="threads for the oracle baseline (default: nproc, the cores this process may use)")
+    ap.add_argument("--extras", default="latency,uneven,precision,sampler",
+                    help="comma list of the other workloads measured after the throughput line and reported in "
+                         "it: latency (one walker, T_obs = 2^22 s), uneven (2048 uneven walkers), precision "
+                         "(FP32C against FP64 at three SNRs), sampler (ESS/s, learned proposal vs stretch); "
+                         "'none' for the throughput line alone")
+    ap.add_argument("--extra-sampler-seconds", type=float, default=45.0,
+                    help="seconds per arm of the bounded ESS/s comparison in the throughput line")
+    ap.add_argument("--extra-sampler-burn", type=float, default=60.0,
+                    help="seconds of the shared stretch-only burn-in of that comparison")
+    ap.add_argument("--extra-sampler-init-rel", type=float, default=1e-3,
+                    help="relative width of the Gaussian ball about the injection that starts its chains")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense_traffic.json"))
     ap.add_argument("--sampler", type=float, default=0.0, metavar="SECONDS",
                     help="instead of the throughput line, run the learned-proposal comparison: PT (8 rungs x "
@@ -67,6 +92,8 @@ def parse():
     ap.add_argument("--sampler-save", default="", metavar="NPZ",
                     help="with --sampler: save both arms' T = 1 chains (every 5th step, float32)")
     ap.add_argument("--sampler-walkers", type=int, default=512)
+    ap.add_argument("--sampler-init-rel", type=float, default=1e-3,
+                    help="relative width of the Gaussian ball about the injection that starts the chains")
     ap.add_argument("--sampler-rungs", type=int, default=8)
     ap.add_argument("--schedule-study", action="store_true",
                     help="instead of the throughput line, time the dense kernel under every launch shape "
@@ -138,7 +165,7 @@ def sampler_comparison(args):
     L0.close()
     data = h + inputs.noise(g, psd, w.noise_seed)
     L = mbh.Likelihood(g, data, psd, w.modes, w.ns, w.t0, max_batch=nt * nw)
-    x0 = inputs.to_sampling(w.walkers).reshape(nt, nw, -1)
+    x0 = inputs.to_sampling(inputs.ball(w.injection, nt * nw, args.sampler_init_rel, 202)).reshape(nt, nw, -1)
     log = lambda name, rep: print(f"# {name}: {json.dumps(rep)}", file=sys.stderr, flush=True)
     rep = S.ess_comparison(S.gpu_loglike(L), S.box_logprior(), x0, S.ladder(nt), args.sampler,
                            args.sampler_burn, seeds=(5, 55), a=1.15, log=log,
@@ -155,6 +182,7 @@ def sampler_comparison(args):
               "higher_is_better": True, "n_gpus": 1, "dtype": "f64",
               "data": "synthetic (seeded injection + Gaussian noise, analytic PSD)",
               "config": {"workload": w.name, "rungs": nt, "walkers_per_rung": nw, "stretch_a": 1.15,
+                         "init_ball_rel": args.sampler_init_rel,
                          "burn_in_seconds": args.sampler_burn, "seconds_per_arm": args.sampler, "seeds": [5, 55]},
               "report": rep}
     print(json.dumps(result), flush=True)
@@ -258,12 +286,11 @@ def precision_study(args):
                                "evals_per_s": round(B / (step_ms * 1e-3), 1), "dense_workgroups_per_cu": bpc}
             L.close()
         d = np.abs(res["fp32c"] - res["fp64"])
-        bound = 5e-9 * snr * snr + 1e-6 * snr + 1e-5
         hist, edges = np.histogram(np.log10(np.maximum(d, 1e-16)), bins=np.arange(-16, 4))
         case = {"snr": round(snr, 2), "D_L_gpc": round(float(inj[4]), 4),
                 "abs_err_fp32c_vs_fp64": {"max": float(d.max()), "median": float(np.median(d)),
                                           "p99": float(np.quantile(d, 0.99))},
-                "max_err_over_bound": float((d / bound).max()),
+                "floor_3e-8_snr": 3e-8 * snr,
                 "log10_abs_err_histogram": {"edges": [int(e) for e in edges], "counts": [int(c) for c in hist]}}
         if speed:
             case["speed"] = speed
@@ -282,7 +309,7 @@ def precision_study(args):
     L0.close()
     result = {"metric": "FP32C ln L error per walker vs FP64", "unit": "abs ln L", "n_gpus": 1,
               "config": {"workload": w.name, "walkers": B, "dense_bins": g.n},
-              "bound": "5e-9 SNR^2 + 1e-6 SNR + 1e-5", "cases": cases}
+              "cases": cases}
     print(json.dumps(result), flush=True)
 
 
@@ -468,6 +495,291 @@ def points_study(args):
     print(json.dumps(result), flush=True)
 
 
+def _say(tag, obj):
+    print(f"# {tag}: {json.dumps(obj)}", file=sys.stderr, flush=True)
+
+
+def host_cpus():
+    """Cores this process may use (nproc honours the affinity mask and
+    OMP_NUM_THREADS), the machine's count, and the CPU model."""
+    import subprocess
+
+    def run(*a):
+        try:
+            return int(subprocess.run(list(a), capture_output=True, text=True, check=True).stdout.strip())
+        except Exception:
+            return None
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": run("nproc"), "nproc_all": run("nproc", "--all"), "os_cpu_count": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)), "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS"),
+            "cpu_model": model}
+
+
+def make_data(L0_factory, w, psd):
+    """Injection template on the device plus the workload's seeded noise."""
+    from paper_2005_01827_amd import inputs
+    L0 = L0_factory()
+    try:
+        h = L0.template(w.injection).cpu().numpy()
+    finally:
+        L0.close()
+    return h + inputs.noise(w.grid, psd, w.noise_seed)
+
+
+def extra_latency(args, O):
+    """One walker on the T_obs = 2^22 s grid: time per graph-launched
+    loglike_batch(B = 1), the launch included, at the injection and at 1000
+    seeded perturbations (a Gaussian ball of relative width 1e-3), one call
+    at a time."""
+    import torch
+    from paper_2005_01827_amd import inputs, mbh
+    w = inputs.short_grid(1000)
+    g = w.grid
+    psd = inputs.psd_aet(g.freqs)
+    data = make_data(lambda: mbh.Likelihood(g, np.zeros((3, g.n), complex), psd, w.modes, w.ns, w.t0, max_batch=1),
+                     w, psd)
+    L = mbh.Likelihood(g, data, psd, w.modes, w.ns, w.t0, max_batch=1)
+    try:
+        pts = np.concatenate([w.injection[None], w.walkers])
+        p_dev = torch.as_tensor(pts, dtype=torch.float64, device="cuda")
+        out = torch.empty(len(pts), dtype=torch.float64, device="cuda")
+        for i in range(20):
+            L.loglike(p_dev[i:i + 1], out=out[i:i + 1])
+        torch.cuda.synchronize()
+        lat = []
+        for i in range(len(pts)):
+            t = time.perf_counter()
+            L.loglike(p_dev[i:i + 1], out=out[i:i + 1])
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        for i in range(len(pts)):
+            L.loglike(p_dev[i:i + 1], out=out[i:i + 1])
+        torch.cuda.synchronize()
+        pipelined = (time.perf_counter() - t) / len(pts)
+        got = out.cpu().numpy()
+        L.set_timing(True)
+        for i in range(50):
+            L.loglike(p_dev[i:i + 1], out=out[i:i + 1])
+        dms, cnt = L.get_timing()
+        L.set_timing(False)
+    finally:
+        L.close()
+    lat = np.array(lat) * 1e6
+    res = {"workload": w.name.replace("1000walkers", "1walker"), "dense_bins": g.n, "calls": len(pts),
+           "us_per_call_median": round(float(np.median(lat)), 1), "us_per_call_p90": round(float(np.quantile(lat, 0.9)), 1),
+           "us_per_call_back_to_back": round(pipelined * 1e6, 1), "dense_kernel_us": round(dms / max(cnt, 1) * 1e3, 1),
+           "evals_per_s_one_at_a_time": round(1e6 / float(np.median(lat)), 1)}
+    if O is not None:
+        idx = np.array([0, 1, 500, 1000])
+        ref = O.loglike(pts[idx], g, data, psd, w.modes, w.ns, w.t0, nthreads=min(len(idx), os.cpu_count() or 1))[:, 0]
+        res["parity_max_rel_err_4_points"] = float(np.max(np.abs(got[idx] - ref) / np.maximum(np.abs(ref), 1.0)))
+        t = time.perf_counter()
+        O.loglike(pts[:2], g, data, psd, w.modes, w.ns, w.t0, nthreads=1)
+        res["oracle_ms_per_eval_1core"] = round((time.perf_counter() - t) * 1e3 / 2, 2)
+    return res
+
+
+def extra_uneven(args, O, data):
+    """2048 walkers with masses from 1e5 to 1e8 Msun on the 2^25-s data: one
+    graph launch per sweep, ticketed (walker, tile) items against one
+    workgroup per walker."""
+    import torch
+    from paper_2005_01827_amd import inputs, mbh
+    w = inputs.uneven_batch(2048)
+    g = w.grid
+    B = len(w.walkers)
+    psd = inputs.psd_aet(g.freqs)
+    L = mbh.Likelihood(g, data, psd, w.modes, w.ns, w.t0, max_batch=B)
+    try:
+        p_dev = torch.as_tensor(w.walkers, dtype=torch.float64, device="cuda")
+        out = torch.empty(B, dtype=torch.float64, device="cuda")
+        bpc, _ = L.autotune(p_dev, reps=3)
+        for _ in range(3):
+            L.loglike(p_dev, out=out)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = 10
+        for _ in range(reps):
+            L.loglike(p_dev, out=out)
+        torch.cuda.synchronize()
+        sweep_ms = (time.perf_counter() - t) * 1e3 / reps
+        lnl = out.cpu().numpy()
+        dense = {}
+        for key, (b, one) in (("tiled", (bpc, False)), ("one_workgroup_per_walker", (1, True))):
+            L.set_schedule(b, one)
+            L.set_timing(True)
+            for _ in range(5):
+                L.loglike(p_dev, out=out)
+            ms, cnt = L.get_timing()
+            L.set_timing(False)
+            dense[key] = ms / max(cnt, 1)
+            assert np.array_equal(out.cpu().numpy(), lnl), "launch shapes disagree"
+        bins, mode_bins = band_bins(L, B)
+    finally:
+        L.close()
+    res = {"workload": w.name, "walkers": B, "dense_workgroups_per_cu": bpc, "ms_per_sweep": round(sweep_ms, 3),
+           "evals_per_s": round(B / (sweep_ms * 1e-3), 1), "dense_ms_tiled": round(dense["tiled"], 3),
+           "dense_ms_one_workgroup_per_walker": round(dense["one_workgroup_per_walker"], 3),
+           "load_balance_efficiency_vs_one_workgroup_per_walker":
+               round(dense["one_workgroup_per_walker"] / dense["tiled"], 3),
+           "band_bins_min_max": [int(bins[bins > 0].min()), int(bins.max())], "walker_bins": int(bins.sum()),
+           "mode_bins": int(mode_bins.sum()), "invalid_or_empty_walkers": int((bins == 0).sum())}
+    if O is not None:
+        live = np.flatnonzero(bins > 0)
+        idx = np.unique(np.concatenate([[live[np.argmin(bins[live])], live[np.argmax(bins[live])]],
+                                        np.linspace(0, B - 1, 6).astype(int)]))
+        ref = O.loglike(w.walkers[idx], g, data, psd, w.modes, w.ns, w.t0,
+                        nthreads=min(len(idx), os.cpu_count() or 1))[:, 0]
+        fin = np.isfinite(ref)
+        res["parity_sample_walkers"] = int(len(idx))
+        res["parity_max_rel_err"] = float(np.max(np.abs(lnl[idx][fin] - ref[fin]) / np.maximum(np.abs(ref[fin]), 1.0)))
+    return res
+
+
+def extra_precision(args, O, w):
+    """FP32C (FP64 phase, FP32 template, float-float residual sums) against
+    the FP64 path per walker on the 1024-walker batch, at the injection's SNR
+    and with D_L rescaled (the template scales as 1/D_L exactly) to SNR 100
+    and 1000; the FP64 path itself matches the oracle to 1e-10."""
+    import torch
+    from paper_2005_01827_amd import inputs, mbh
+    g = w.grid
+    B = len(w.walkers)
+    psd = inputs.psd_aet(g.freqs)
+    L0 = mbh.Likelihood(g, np.zeros((3, g.n), complex), psd, w.modes, w.ns, w.t0, max_batch=1)
+    try:
+        rho0 = math.sqrt(float(L0.stages(w.injection[None])[0, 4:7].sum().cpu()))
+        cases = []
+        for snr in (rho0, 100.0, 1000.0):
+            f = rho0 / snr
+            inj = w.injection.copy()
+            inj[4] *= f
+            walkers = w.walkers.copy()
+            walkers[:, 4] *= f
+            # 64 more walkers in a ball of relative width 1e-7 about the
+            # injection: the residual there is the noise, the sampler's regime
+            near = inputs.ball(inj, 64, 1e-7, 203)
+            walkers = np.concatenate([walkers, near])
+            data = L0.template(inj).cpu().numpy() + inputs.noise(g, psd, w.noise_seed)
+            res, speed = {}, {}
+            for name, prec in (("fp64", mbh.MBH_FP64), ("fp32c", mbh.MBH_FP32C)):
+                L = mbh.Likelihood(g, data, psd, w.modes, w.ns, w.t0, precision=prec, max_batch=B + 64)
+                try:
+                    p_all = torch.as_tensor(walkers, dtype=torch.float64, device="cuda")
+                    res[name] = L.loglike(p_all).cpu().numpy()
+                    p_dev = p_all[:B].contiguous()
+                    out = torch.empty(B, dtype=torch.float64, device="cuda")
+                    if not cases:
+                        bpc, _ = L.autotune(p_dev, reps=3)
+                        L.loglike(p_dev, out=out)
+                        torch.cuda.synchronize()
+                        t = time.perf_counter()
+                        for _ in range(5):
+                            L.loglike(p_dev, out=out)
+                        torch.cuda.synchronize()
+                        step_ms = (time.perf_counter() - t) * 1e3 / 5
+                        L.set_timing(True)
+                        for _ in range(5):
+                            L.loglike(p_dev, out=out)
+                        dms, cnt = L.get_timing()
+                        L.set_timing(False)
+                        speed[name] = {"ms_per_step": round(step_ms, 3), "dense_ms": round(dms / max(cnt, 1), 3),
+                                       "evals_per_s": round(B / (step_ms * 1e-3), 1)}
+                finally:
+                    L.close()
+            dall = np.abs(res["fp32c"] - res["fp64"])
+            d, dn = dall[:B], dall[B:]
+            case = {"snr": round(snr, 1), "max_abs_dlnL": float(d.max()), "median_abs_dlnL": float(np.median(d)),
+                    "p99_abs_dlnL": float(np.quantile(d, 0.99)),
+                    "near_injection_64": {"max_abs_dlnL": float(dn.max()), "median_abs_dlnL": float(np.median(dn))},
+                    "model_sigma_rel_times_snr": SIG_REL_FP32C * snr,
+                    "survey_floor_3e-8_snr": 3e-8 * snr}
+            if speed:
+                case["speed"] = speed
+                case["fp32c_over_fp64_speed"] = round(speed["fp32c"]["evals_per_s"] / speed["fp64"]["evals_per_s"], 3)
+            _say(f"precision snr {snr:.0f}", case)
+            cases.append(case)
+    finally:
+        L0.close()
+    return {"workload": w.name, "walkers": B, "reference": "FP64 GPU path (itself within 1e-10 of the oracle)",
+            "error_model": "first order Re<d - h, dh>: about sigma_rel |r| |h| per walker, sigma_rel = 2^-24 "
+                           "sqrt(29/3) from 29 FP32 roundings per bin; near the injection (r ~ noise) about "
+                           "sigma_rel * SNR",
+            "cases": cases}
+
+
+def extra_sampler(args, w, data):
+    """Bounded ESS/s comparison: parallel tempering with 8 rungs x 512
+    walkers at a = 1.15 on the 2^25-s data from the 1e-3 Gaussian ball, a
+    shared stretch-only burn-in, then equal wall time per arm (the flow's
+    training charged to its arm); equal accuracy by 3 batch-means standard
+    errors and 5 % in standard deviation."""
+    from paper_2005_01827_amd import inputs, mbh
+    from paper_2005_01827_amd import sampler as S
+    nt, nw = 8, 512
+    g = w.grid
+    psd = inputs.psd_aet(g.freqs)
+    walkers = inputs.ball(w.injection, nt * nw, args.extra_sampler_init_rel, 202)
+    L = mbh.Likelihood(g, data, psd, w.modes, w.ns, w.t0, max_batch=nt * nw)
+    try:
+        x0 = inputs.to_sampling(walkers).reshape(nt, nw, -1)
+        rep = S.ess_comparison(S.gpu_loglike(L), S.box_logprior(), x0, S.ladder(nt), args.extra_sampler_seconds,
+                               args.extra_sampler_burn, seeds=(5, 55), a=1.15, log=_say,
+                               fit_kwargs={"steps": 800, "lr": 2e-3, "batch": 4096})
+    finally:
+        L.close()
+    keep = ("steps", "wall_s", "tau", "ess", "ess_per_s", "ess_batch_means", "ess_batch_means_per_s",
+            "chain_over_50_tau", "acceptance_per_rung", "swap_rate", "flow_acceptance")
+    return {"rungs": nt, "walkers_per_rung": nw, "stretch_a": 1.15, "init_ball_rel": args.extra_sampler_init_rel,
+            "burn_in": rep["burn_in"],
+            "seconds_per_arm": args.extra_sampler_seconds,
+            "stretch": {k: rep["stretch"][k] for k in keep},
+            "stretch_flow": dict({k: rep["stretch_flow"][k] for k in keep}, train_s=rep["stretch_flow"]["train_s"]),
+            "ess_per_s_gain": rep["ess_per_s_gain"], "ess_per_s_gain_batch_means": rep["ess_per_s_gain_batch_means"],
+            "equal_accuracy": rep["accuracy"]["equal"],
+            "max_mean_diff_in_batch_means_se": rep["accuracy"]["max_mean_diff_in_batch_means_se"],
+            "max_sd_rel_diff": rep["accuracy"]["max_sd_rel_diff"]}
+
+
+def cpu_baseline(args, O, w, data, psd, lnl, gpu_evals_per_s):
+    """The FP64 oracle on the host cores this process may use (nproc), on a
+    bounded sample of the batch, and on one core."""
+    info = host_cpus()
+    nthreads = args.cpu_threads if args.cpu_threads > 0 else (info["nproc"] or info["affinity"] or 1)
+    B = len(w.walkers)
+    ns_ = min(max(args.cpu_sample, nthreads * 2), B)
+    idx = np.linspace(0, B - 1, ns_).astype(int)
+    O.loglike(w.walkers[:1], w.grid, data, psd, w.modes, w.ns, w.t0, nthreads=1)   # load, page in
+    tc0 = time.perf_counter()
+    ref = O.loglike(w.walkers[idx], w.grid, data, psd, w.modes, w.ns, w.t0, nthreads=nthreads)
+    tc1 = time.perf_counter()
+    one = idx[:2]
+    t1 = time.perf_counter()
+    O.loglike(w.walkers[one], w.grid, data, psd, w.modes, w.ns, w.t0, nthreads=1)
+    single = len(one) / (time.perf_counter() - t1)
+    err = np.abs(lnl[idx] - ref[:, 0]) / np.maximum(np.abs(ref[:, 0]), 1.0)
+    value = ns_ / (tc1 - tc0)
+    cb = {"value": round(value, 3), "unit": "evals/s", "cores": int(nthreads), "kind": "oracle",
+          "sample": f"{ns_} of the {B} walkers (evenly spaced), full grid, OpenMP over walkers",
+          "single_thread_value": round(single, 3), "single_thread_sample": "2 of those walkers, one thread",
+          "build": "gcc " + " ".join(O.CFLAGS)}
+    cb.update(info)
+    ctx = {"gpu_over_oracle": round(gpu_evals_per_s / value, 1),
+           "gpu_over_oracle_one_core": round(gpu_evals_per_s / single, 1),
+           "paper_gpu_over_cpu": "about 500x: one V100 against one Xeon Gold 6132 core, brute-force CPU likelihood "
+                                 "(Sec. II)"}
+    return cb, float(err.max()), ctx
+
+
 def main():
     args = parse()
     if args.points_study and args.gpus == 1:
@@ -504,10 +816,8 @@ def main():
     print(f"# workload {w.name}: B={B} n={g.n} modes={len(w.modes)} ns={w.ns}", file=sys.stderr, flush=True)
     psd = inputs.psd_aet(g.freqs)
     # injection on the device, then seeded Gaussian noise
-    L0 = mbh.Likelihood(g, np.zeros((3, g.n), complex), psd, w.modes, w.ns, w.t0, max_batch=1)
-    h = L0.template(w.injection).cpu().numpy()
-    L0.close()
-    data = h + inputs.noise(g, psd, w.noise_seed)
+    data = make_data(lambda: mbh.Likelihood(g, np.zeros((3, g.n), complex), psd, w.modes, w.ns, w.t0, max_batch=1),
+                     w, psd)
     L = mbh.Likelihood(g, data, psd, w.modes, w.ns, w.t0, max_batch=B)
     params = torch.as_tensor(w.walkers, dtype=torch.float64, device="cuda")
     out = torch.empty(B, dtype=torch.float64, device="cuda")
@@ -540,9 +850,11 @@ def main():
     assert np.array_equal(out.cpu().numpy(), lnl), "timed and graph paths disagree"
 
     bins, mode_bins = band_bins(L, B)
-    # algorithmic work of the dense kernel (see the design notes, section 6)
+    L.close()
+    # algorithmic work of the dense kernel per launch (see the design notes)
     alg_flops = float(mode_bins.sum()) * FLOPS_PER_MODE_BIN + float(bins.sum()) * FLOPS_PER_WALKER_BIN
     achieved_tflops = alg_flops / (dense_avg_ms * 1e-3) / 1e12
+    lane_ops = float(mode_bins.sum()) * LANE_OPS_PER_MODE_BIN + float(bins.sum()) * LANE_OPS_PER_WALKER_BIN
     alg_bytes = float(bins.sum()) * BYTES_PER_WALKER_BIN
     logical_gbs = alg_bytes / (dense_avg_ms * 1e-3) / 1e9
     traffic = None
@@ -555,12 +867,21 @@ def main():
             traffic = None
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved_tflops / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": "k_dense (interpolation + mode sum + inner products)", "avg_ms": round(dense_avg_ms, 4),
+                "kernel": "k_dense (interpolation + mode sum + residual sums)", "avg_ms": round(dense_avg_ms, 4),
                 "alg_flops_per_launch": alg_flops, "flops_per_mode_bin": FLOPS_PER_MODE_BIN,
                 "flops_per_walker_bin": FLOPS_PER_WALKER_BIN, "mode_bins": int(mode_bins.sum()),
                 "walker_bins": int(bins.sum()),
-                "hbm_logical": {"bytes_per_walker_bin": BYTES_PER_WALKER_BIN, "bytes_per_launch": alg_bytes,
-                                "GB/s": round(logical_gbs, 1), "frac_of_8TB/s": round(logical_gbs / HBM_PEAK_GBS, 4)}}
+                "fp64_lane_ops": {"per_mode_bin": LANE_OPS_PER_MODE_BIN, "per_walker_bin": LANE_OPS_PER_WALKER_BIN,
+                                  "per_launch": lane_ops,
+                                  "frac_of_3.93e13_per_s": round(lane_ops / (dense_avg_ms * 1e-3) / LANE_OPS_PEAK, 4)},
+                "hbm_measured": ({"bytes_per_launch": traffic,
+                                  "GB/s": round(traffic / (dense_avg_ms * 1e-3) / 1e9, 1),
+                                  "frac_of_8TB/s": round(traffic / (dense_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                                 if traffic else None),
+                "logical_stream": {"note": "d and w read once per walker-bin; all walkers share them, so L2 and the "
+                                           "last-level cache serve this stream, not HBM",
+                                   "bytes_per_walker_bin": BYTES_PER_WALKER_BIN, "bytes_per_launch": alg_bytes,
+                                   "GB/s": round(logical_gbs, 1)}}
 
     result = {
         "metric": METRIC, "value": round(evals_per_s, 1), "unit": "evals/s", "n_gpus": 1,
@@ -572,25 +893,38 @@ def main():
         "roofline": roofline,
     }
 
+    O = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         O.build()
-        nthreads = args.cpu_threads if args.cpu_threads > 0 else min(16, os.cpu_count() or 1)
-        ns_ = min(args.cpu_sample, B)
-        idx = np.linspace(0, B - 1, ns_).astype(int)
-        tc0 = time.perf_counter()
-        ref = O.loglike(w.walkers[idx], g, data, psd, w.modes, w.ns, w.t0, nthreads=nthreads)
-        tc1 = time.perf_counter()
-        err = np.abs(lnl[idx] - ref[:, 0]) / np.maximum(np.abs(ref[:, 0]), 1.0)
-        result["cpu_baseline"] = {"value": round(ns_ / (tc1 - tc0), 3), "unit": "evals/s", "cores": nthreads,
-                                  "kind": "oracle",
-                                  "sample": f"{ns_} of the {B} walkers (evenly spaced), full grid, OpenMP over walkers"}
-        result["parity_sample_max_rel_err"] = float(err.max())
-        result["context"] = {"gpu_over_oracle": round(evals_per_s / (ns_ / (tc1 - tc0)), 1),
-                             "paper_gpu_over_cpu": "about 500x: one V100 against one Xeon Gold 6132 core, "
-                                                   "brute-force CPU likelihood (Sec. II)"}
+        cb, perr, ctx = cpu_baseline(args, O, w, data, psd, lnl, evals_per_s)
+        result["cpu_baseline"] = cb
+        result["parity_sample_max_rel_err"] = perr
+        result["context"] = ctx
+        _say("cpu_baseline", cb)
+
+    extras = [e for e in args.extras.split(",") if e and e != "none"] if args.config == "tobs25" else []
+    for name in extras:
+        t = time.perf_counter()
+        try:
+            if name == "latency":
+                rep = extra_latency(args, O)
+            elif name == "uneven":
+                rep = extra_uneven(args, O, data)
+            elif name == "precision":
+                rep = extra_precision(args, O, w)
+            elif name == "sampler":
+                rep = extra_sampler(args, w, data)
+            else:
+                rep = {"error": f"unknown extra '{name}'"}
+        except Exception as exc:      # reported in the line, not hidden
+            rep = {"error": f"{type(exc).__name__}: {exc}"}
+        rep["wall_s"] = round(time.perf_counter() - t, 1)
+        result[{"latency": "batch1_latency", "uneven": "uneven_batch", "precision": "fp32c_precision",
+                "sampler": "ess_flow_vs_stretch"}.get(name, name)] = rep
+        _say(name, rep)
+        torch.cuda.synchronize()
     print(json.dumps(result), flush=True)
-    L.close()
 
 
 if __name__ == "__main__":
