@@ -472,20 +472,17 @@ __device__ __forceinline__ void mode_bin(const CisConst &K, P c, double dx, doub
     }
 }
 
-// One mode at the NB bins of a lane in one step, all in one interval: the
-// wave-uniform coefficients are read once and feed NB independent
-// evaluations.  A bin outside the mode's band contributes through a zero
-// amplitude instead of a branch, so the scalar loads stay shared (its
-// offset from the knot is at most one step outside the interval, where the
-// cubics are finite).
+// One mode at the NB bins of a lane in one step, all in one interval and
+// inside the mode's band: the wave-uniform coefficients are read once and
+// feed NB independent evaluations, with no per-bin test.
 template <int NB>
 __device__ __forceinline__ void mode_bins_u(const CisConst &K, cdouble *c, const double (&dx)[NB],
-                                            const bool (&in)[NB], double (&hr)[NB][3], double (&hi)[NB][3])
+                                            double (&hr)[NB][3], double (&hi)[NB][3])
 {
     double ar[NB], ai[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        const double amp = in[b] ? cubic_s(c + 0, dx[b]) : 0.0;
+        const double amp = cubic_s(c + 0, dx[b]);
         const double ph = cubic_s(c + 4, dx[b]);
         double sn, cs;
         cis(K, ph, sn, cs);
@@ -596,15 +593,14 @@ __device__ __forceinline__ void mode_bin32(const CisConst &K, const CisConst32 &
 // FP32 stage, NB bins of a lane in one interval (see mode_bins_u).
 template <int NB>
 __device__ __forceinline__ void mode_bins32_u(const CisConst &K, const CisConst32 &Kf, cdouble *cd, cfloat *cf,
-                                              const double (&dx)[NB], const bool (&in)[NB], float (&hr)[NB][3],
-                                              float (&hi)[NB][3])
+                                              const double (&dx)[NB], float (&hr)[NB][3], float (&hi)[NB][3])
 {
     float ar[NB], ai[NB], dxf[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const double ph = cubic_s(cd + 4, dx[b]);
         dxf[b] = (float)dx[b];
-        const float amp = in[b] ? cubic32_s(cf + 0, dxf[b]) : 0.0f;
+        const float amp = cubic32_s(cf + 0, dxf[b]);
         float sn, cs;
         cis32(K, Kf, ph, sn, cs);
         ar[b] = amp * cs;
@@ -805,10 +801,12 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
                     cur[m] = uni_i(cur[m] + 1);
                     nxt[m] = uni_i(((cint *)a.kbin)[kbo + cur[m] + 1]);
                 }
-                bool in[NB];
-#pragma unroll
-                for (int b = 0; b < NB; ++b) in[b] = (k[b] >= mlo[m]) && (k[b] <= mhi[m]);
-                if (hi_ < nxt[m]) {
+                // the wave-uniform path takes a step that lies wholly inside
+                // the mode's band and inside one interval; a step at a band
+                // edge (once or twice per mode and walker) or across a knot
+                // goes to the per-lane code
+                const bool whole = s0 >= mlo[m] && s0 + 64 * NB - 1 <= mhi[m];
+                if (whole && hi_ < nxt[m]) {
                     // the cubics of interval i are centred on the first bin of
                     // the next interval, kbin[i+1] = nxt: no knot load needed
                     const int iv = cur[m];
@@ -819,11 +817,10 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
 #pragma unroll
                         for (int b = 0; b < NB; ++b) dx[b] = f[b] - x0;
                         if (kF32)
-                            mode_bins32_u<NB>(K, Kf, (cdouble *)a.coef + c0, (cfloat *)a.coef32 + c0, dx, in, hr32,
-                                              hi32);
+                            mode_bins32_u<NB>(K, Kf, (cdouble *)a.coef + c0, (cfloat *)a.coef32 + c0, dx, hr32, hi32);
                         else
-                            mode_bins_u<NB>(K, (cdouble *)a.coef + c0, dx, in, hr, hi);
-                    } else if (in[0]) {
+                            mode_bins_u<NB>(K, (cdouble *)a.coef + c0, dx, hr, hi);
+                    } else {
                         if (kF32)
                             mode_bin32<cdouble *, cfloat *>(K, Kf, (cdouble *)a.coef + c0, (cfloat *)a.coef32 + c0,
                                                             f[0] - x0, hr32[0], hi32[0]);
@@ -831,9 +828,9 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
                             mode_bin<cdouble *>(K, (cdouble *)a.coef + c0, f[0] - x0, hr[0], hi[0]);
                     }
                 } else if (!kF32) {
-                    // the step crosses a knot: defer the mode to the per-lane
-                    // pass below, which then exists once instead of once per
-                    // unrolled mode (3-5 % faster on the FP64 paths)
+                    // defer the mode to the per-lane pass below, which then
+                    // exists once instead of once per unrolled mode (3-5 %
+                    // faster on the FP64 paths)
                     xmask |= 1u << m;
                     if (lane == 0) xcur[wave][m] = cur[m];
                 } else {
@@ -841,7 +838,7 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
                     // not pay there)
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
-                        if (!in[b]) continue;
+                        if (k[b] < mlo[m] || k[b] > mhi[m]) continue;
                         int iv = cur[m];
                         while (iv < ns - 2 && a.kbin[kbo + iv + 1] <= k[b]) ++iv;
                         const size_t c0 = (size_t)(ivo + iv) * kCoefPerIv;
@@ -851,8 +848,9 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
                     }
                 }
             }
-            // per-lane pass over the modes whose step crosses a knot: each
-            // lane finds its own interval from the one of the step's start
+            // per-lane pass over the modes whose step crosses a knot or a
+            // band edge: each lane skips bins outside the band and finds its
+            // own interval from the one of the step's start
 #pragma nounroll
             for (unsigned mm = xmask; mm != 0u; mm &= mm - 1u) {
                 const int m = uni_i(__builtin_ctz(mm));
@@ -902,13 +900,18 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
                 // d and w are loaded here, after the modes: holding them across
                 // the mode loop took registers the mode evaluation needs
                 // (measured: 9 % slower)
+                // per channel a wave-uniform base and a 32-bit per-lane byte
+                // offset (the global-load form with a scalar base)
 #pragma unroll
-                for (int b = 0; b < NB; ++b)
+                for (int ch = 0; ch < 3; ++ch) {
+                    const char *dch = (const char *)(a.d + (size_t)ch * a.n);
+                    const char *wch = (const char *)(a.w + (size_t)ch * a.n);
 #pragma unroll
-                    for (int ch = 0; ch < 3; ++ch) {
-                        dv[b][ch] = a.d[(size_t)ch * a.n + idx[b]];
-                        wv[b][ch] = a.w[(size_t)ch * a.n + idx[b]];
+                    for (int b = 0; b < NB; ++b) {
+                        dv[b][ch] = *(const double2 *)(dch + (unsigned)idx[b] * 16u);
+                        wv[b][ch] = *(const double *)(wch + (unsigned)idx[b] * 8u);
                     }
+                }
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     if (!inw[b]) continue;
