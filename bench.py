@@ -80,8 +80,10 @@ def parse():
                     help="seconds per arm of the bounded ESS/s comparison in the throughput line")
     ap.add_argument("--extra-sampler-burn", type=float, default=60.0,
                     help="seconds of the shared stretch-only burn-in of that comparison")
+    ap.add_argument("--extra-sampler-init", default="curvature", choices=["curvature", "ball"],
+                    help="start of its chains (as --sampler-init)")
     ap.add_argument("--extra-sampler-init-rel", type=float, default=1e-3,
-                    help="relative width of the Gaussian ball about the injection that starts its chains")
+                    help="relative width of the Gaussian ball (--extra-sampler-init ball)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense_traffic.json"))
     ap.add_argument("--sampler", type=float, default=0.0, metavar="SECONDS",
                     help="instead of the throughput line, run the learned-proposal comparison: PT (8 rungs x "
@@ -92,8 +94,12 @@ def parse():
     ap.add_argument("--sampler-save", default="", metavar="NPZ",
                     help="with --sampler: save both arms' T = 1 chains (every 5th step, float32)")
     ap.add_argument("--sampler-walkers", type=int, default=512)
+    ap.add_argument("--sampler-init", default="curvature", choices=["curvature", "ball"],
+                    help="start of the chains: the Gaussian approximation of the posterior at the injection "
+                         "(covariance from the Hessian of ln L, widened by each rung's temperature), or a "
+                         "Gaussian ball of relative width --sampler-init-rel about the injection")
     ap.add_argument("--sampler-init-rel", type=float, default=1e-3,
-                    help="relative width of the Gaussian ball about the injection that starts the chains")
+                    help="relative width of the Gaussian ball about the injection (--sampler-init ball)")
     ap.add_argument("--sampler-rungs", type=int, default=8)
     ap.add_argument("--schedule-study", action="store_true",
                     help="instead of the throughput line, time the dense kernel under every launch shape "
@@ -165,7 +171,7 @@ def sampler_comparison(args):
     L0.close()
     data = h + inputs.noise(g, psd, w.noise_seed)
     L = mbh.Likelihood(g, data, psd, w.modes, w.ns, w.t0, max_batch=nt * nw)
-    x0 = inputs.to_sampling(inputs.ball(w.injection, nt * nw, args.sampler_init_rel, 202)).reshape(nt, nw, -1)
+    x0 = start_positions(args.sampler_init, args.sampler_init_rel, L, w, nt, nw)
     log = lambda name, rep: print(f"# {name}: {json.dumps(rep)}", file=sys.stderr, flush=True)
     rep = S.ess_comparison(S.gpu_loglike(L), S.box_logprior(), x0, S.ladder(nt), args.sampler,
                            args.sampler_burn, seeds=(5, 55), a=1.15, log=log,
@@ -182,11 +188,23 @@ def sampler_comparison(args):
               "higher_is_better": True, "n_gpus": 1, "dtype": "f64",
               "data": "synthetic (seeded injection + Gaussian noise, analytic PSD)",
               "config": {"workload": w.name, "rungs": nt, "walkers_per_rung": nw, "stretch_a": 1.15,
-                         "init_ball_rel": args.sampler_init_rel,
+                         "init": args.sampler_init, "init_ball_rel": args.sampler_init_rel,
                          "burn_in_seconds": args.sampler_burn, "seconds_per_arm": args.sampler, "seeds": [5, 55]},
               "report": rep}
     print(json.dumps(result), flush=True)
     L.close()
+
+
+def start_positions(kind, rel, L, w, nt, nw):
+    """PT start [nt][nw][11] in sampling coordinates: the curvature start
+    (sampler.curvature_start at the injection) or a Gaussian ball."""
+    from paper_2005_01827_amd import inputs
+    from paper_2005_01827_amd import sampler as S
+    if kind == "curvature":
+        x0, _ = S.curvature_start(S.gpu_loglike(L), S.box_logprior(), inputs.to_sampling(w.injection),
+                                  S.ladder(nt), nw, seed=202)
+        return x0
+    return inputs.to_sampling(inputs.ball(w.injection, nt * nw, rel, 202)).reshape(nt, nw, -1)
 
 
 def schedule_study(args):
@@ -719,7 +737,8 @@ def extra_precision(args, O, w):
 
 def extra_sampler(args, w, data):
     """Bounded ESS/s comparison: parallel tempering with 8 rungs x 512
-    walkers at a = 1.15 on the 2^25-s data from the 1e-3 Gaussian ball, a
+    walkers at a = 1.15 on the 2^25-s data, started from the Gaussian
+    approximation of the posterior at the injection (or the 1e-3 ball), a
     shared stretch-only burn-in, then equal wall time per arm (the flow's
     training charged to its arm); equal accuracy by 3 batch-means standard
     errors and 5 % in standard deviation."""
@@ -728,10 +747,9 @@ def extra_sampler(args, w, data):
     nt, nw = 8, 512
     g = w.grid
     psd = inputs.psd_aet(g.freqs)
-    walkers = inputs.ball(w.injection, nt * nw, args.extra_sampler_init_rel, 202)
     L = mbh.Likelihood(g, data, psd, w.modes, w.ns, w.t0, max_batch=nt * nw)
     try:
-        x0 = inputs.to_sampling(walkers).reshape(nt, nw, -1)
+        x0 = start_positions(args.extra_sampler_init, args.extra_sampler_init_rel, L, w, nt, nw)
         rep = S.ess_comparison(S.gpu_loglike(L), S.box_logprior(), x0, S.ladder(nt), args.extra_sampler_seconds,
                                args.extra_sampler_burn, seeds=(5, 55), a=1.15, log=_say,
                                fit_kwargs={"steps": 800, "lr": 2e-3, "batch": 4096})
@@ -739,7 +757,8 @@ def extra_sampler(args, w, data):
         L.close()
     keep = ("steps", "wall_s", "tau", "ess", "ess_per_s", "ess_batch_means", "ess_batch_means_per_s",
             "chain_over_50_tau", "acceptance_per_rung", "swap_rate", "flow_acceptance")
-    return {"rungs": nt, "walkers_per_rung": nw, "stretch_a": 1.15, "init_ball_rel": args.extra_sampler_init_rel,
+    return {"rungs": nt, "walkers_per_rung": nw, "stretch_a": 1.15, "init": args.extra_sampler_init,
+            "init_ball_rel": args.extra_sampler_init_rel,
             "burn_in": rep["burn_in"],
             "seconds_per_arm": args.extra_sampler_seconds,
             "stretch": {k: rep["stretch"][k] for k in keep},

@@ -303,8 +303,11 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
             return st;               \
         }                            \
     } while (0)
-    TRY(dalloc(c, &c->d, (size_t)3 * n));
-    TRY(dalloc(c, &c->w, (size_t)3 * n));
+    const size_t n_pad = (size_t)data_padded(n);
+    double2 *d_in = nullptr;      // the data as uploaded, [3][n]; freed after set-up
+    TRY(dalloc(c, &c->d, 3 * n_pad));
+    TRY(dalloc(c, &c->w, 3 * n_pad));
+    TRY(dalloc(c, &d_in, (size_t)3 * n));
     TRY(dalloc(c, &c->pre, (size_t)3 * (n + 1)));
     TRY(dalloc(c, &psd_dev, (size_t)3 * n));
     TRY(dalloc(c, &scratch, (size_t)3 * n + 3 * nchunks));
@@ -340,21 +343,20 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
     const float *cis32_host = cis32_table_host(&ncis32);
     if ((e = hipMemcpy(c->wk.cis_tab, cis_host, sizeof(double) * ncis, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->wk.cis32, cis32_host, sizeof(float) * ncis32, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(c->d, desc->data, sizeof(double) * 6 * n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_in, desc->data, sizeof(double) * 6 * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(c->wk.src, 0, sizeof(Source) * B)) != hipSuccess ||
         (e = hipMemset(c->wk.band, 0, sizeof(ModeBand) * B * nm)) != hipSuccess ||
         (e = hipMemcpy(psd_dev, desc->psd, sizeof(double) * 3 * n, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = launch_setup_data(psd_dev, c->d, c->w, c->pre, scratch, c->dhi32, c->dlo32, c->sw32, c->g, 4.0 * desc->df,
-                           nullptr)) !=
-            hipSuccess ||
+        (e = launch_setup_data(psd_dev, d_in, c->d, c->w, c->pre, scratch, c->dhi32, c->dlo32, c->sw32, c->g,
+                               4.0 * desc->df, nullptr)) != hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess) {
         release(c);
         delete c;
         return MBH_EHIP;
     }
-    // the PSD copy and setup scratch are no longer needed
+    // the uploaded data, the PSD copy and the setup scratch are no longer needed
     for (auto it = c->allocs.begin(); it != c->allocs.end();) {
-        if (*it == psd_dev || *it == scratch) {
+        if (*it == psd_dev || *it == scratch || *it == d_in) {
             (void)hipFree(*it);
             it = c->allocs.erase(it);
         } else {

@@ -32,15 +32,27 @@ constexpr int kScanThreads = 256;
 constexpr int kScanPer = 8;
 constexpr int kScanChunk = kScanThreads * kScanPer;
 
-__global__ void k_weights(const double *__restrict__ psd, const double2 *__restrict__ d, double *__restrict__ w,
-                          double *__restrict__ e2, float2 *__restrict__ dhi32, float2 *__restrict__ dlo32,
-                          float *__restrict__ sw32, long long total, double df4)
+// one thread per (channel, padded bin); grid over 3 n_pad
+__global__ void k_weights(const double *__restrict__ psd, const double2 *__restrict__ d_in,
+                          double2 *__restrict__ d, double *__restrict__ w, double *__restrict__ e2,
+                          float2 *__restrict__ dhi32, float2 *__restrict__ dlo32, float *__restrict__ sw32,
+                          long long n, long long n_pad, double df4)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * n_pad) return;
+    const int ch = (int)(t / n_pad);
+    const long long k = t - ch * n_pad;
+    const long long o = data_at(ch, k);
+    if (k >= n) {
+        d[o] = make_double2(0.0, 0.0);
+        w[o] = 0.0;
+        return;
+    }
+    const long long i = ch * n + k;
     const double wi = df4 / psd[i];
-    w[i] = wi;
-    const double2 di = d[i];
+    const double2 di = d_in[i];
+    w[o] = wi;
+    d[o] = di;
     e2[i] = (di.x * di.x + di.y * di.y) * wi;
     if (dhi32) {
         // whitened data d sqrt(w) as an FP32 pair hi + lo (about 48 bits), so
@@ -732,17 +744,26 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
             if (m < a.nm) {
                 const ModeBand mb = a.band[wk * a.nm + m];
                 if (mb.active && mb.khi >= kw && mb.klo <= kwl) {
-                    cint *kb = (cint *)(a.kbin + (size_t)(wk * a.nm + m) * ns);
+                    const int kbo = (wk * a.nm + m) * ns;
+                    cint *kb = (cint *)(a.kbin + kbo);
                     const int kfirst = uni_i(max(kw, mb.klo));
-                    // largest i in [0, ns-2] with kb[i] <= kfirst: a binary
-                    // search on wave-uniform integers (scalar unit only)
-                    int i = 0, ihi = ns - 2;
-                    while (i < ihi) {
-                        const int mid = (i + ihi + 1) >> 1;
-                        if (kb[mid] <= kfirst) i = mid;
-                        else ihi = mid - 1;
+                    // largest i in [0, ns-2] with kb[i] <= kfirst, i.e. the
+                    // number of such entries less one (kb is nondecreasing):
+                    // every lane tests ns/64 entries and the wavefront counts
+                    // the hits, one round of independent loads instead of a
+                    // chain of log2(ns) dependent ones
+                    int cnt = 0;
+                    for (int j0 = 0; j0 < ns - 1; j0 += 256) {
+                        int v[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int j = j0 + 64 * u + lane;
+                            v[u] = j < ns - 1 ? a.kbin[kbo + j] : 0x7fffffff;
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) cnt += __popcll(__ballot(v[u] <= kfirst));
                     }
-                    i = uni_i(i);
+                    const int i = uni_i(max(cnt - 1, 0));
                     mlo[m] = uni_i(mb.klo);
                     mhi[m] = uni_i(mb.khi);
                     cur[m] = i;
@@ -899,17 +920,20 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
             } else {
                 // d and w are loaded here, after the modes: holding them across
                 // the mode loop took registers the mode evaluation needs
-                // (measured: 9 % slower)
-                // per channel a wave-uniform base and a 32-bit per-lane byte
-                // offset (the global-load form with a scalar base)
+                // (measured: 9 % slower).  Bins s0 + 64 b + lane form block
+                // (s0 - k0)/64 + b of the blocked layout: one wave-uniform
+                // block address, the lane's element, and the channel as an
+                // immediate offset.  Lanes outside the walker's band read
+                // real (or padding) values that the sums below skip.
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    const char *dch = (const char *)(a.d + (size_t)ch * a.n);
-                    const char *wch = (const char *)(a.w + (size_t)ch * a.n);
+                for (int b = 0; b < NB; ++b) {
+                    const long long blk = uni_i((s0 - a.k0) / kDataBlk + b);
+                    const char *db = (const char *)(a.d + blk * (3 * kDataBlk));
+                    const char *wb = (const char *)(a.w + blk * (3 * kDataBlk));
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        dv[b][ch] = *(const double2 *)(dch + (unsigned)idx[b] * 16u);
-                        wv[b][ch] = *(const double *)(wch + (unsigned)idx[b] * 8u);
+                    for (int ch = 0; ch < 3; ++ch) {
+                        dv[b][ch] = *(const double2 *)(db + ((unsigned)lane * 16u + ch * kDataBlk * 16u));
+                        wv[b][ch] = *(const double *)(wb + ((unsigned)lane * 8u + ch * kDataBlk * 8u));
                     }
                 }
 #pragma unroll
@@ -1115,15 +1139,17 @@ hipError_t launch_coef32(int B, const Modes &md, const GridDesc &g, const Work &
     return hipGetLastError();
 }
 
-hipError_t launch_setup_data(const double *psd, const double2 *d, double *w, double *pre, double *scratch,
-                             float2 *dhi32, float2 *dlo32, float *sw32, const GridDesc &g, double df4,
-                             hipStream_t st)
+hipError_t launch_setup_data(const double *psd, const double2 *d_in, double2 *d, double *w, double *pre,
+                             double *scratch, float2 *dhi32, float2 *dlo32, float *sw32, const GridDesc &g,
+                             double df4, hipStream_t st)
 {
     const long long total = 3LL * g.n;
+    const long long n_pad = data_padded(g.n);
     double *e2 = scratch;                  // [3][n]
     const int nchunks = (g.n + kScanChunk - 1) / kScanChunk;
     double *chunk = scratch + total;       // [3][nchunks]
-    k_weights<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(psd, d, w, e2, dhi32, dlo32, sw32, total, df4);
+    k_weights<<<(unsigned)((3 * n_pad + 255) / 256), 256, 0, st>>>(psd, d_in, d, w, e2, dhi32, dlo32, sw32, g.n,
+                                                                   n_pad, df4);
     k_scan_chunks<<<dim3(nchunks, 3), kScanThreads, 0, st>>>(e2, g.n, chunk, nchunks);
     k_scan_offsets<<<3, kScanThreads, 0, st>>>(chunk, nchunks);
     k_scan_final<<<dim3(nchunks, 3), kScanThreads, 0, st>>>(e2, g.n, chunk, nchunks, pre);

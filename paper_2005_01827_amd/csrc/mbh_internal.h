@@ -109,10 +109,24 @@ struct Work {
     float *coef32;          // [B][nm][ns-1][32] FP32 copy of coef (FP32 dense stage)
 };
 
+// Blocked layout of the data and weights read by the dense stage: bins in
+// blocks of 64, each block holding the 64 values of channel A, then E, then
+// T, so that a wavefront's 64 consecutive bins of all three channels are one
+// wave-uniform block address plus lane * element size and an immediate
+// channel offset.  The arrays are padded with zeros to a multiple of
+// kDataPad bins, past the end of the last tile a dense launch can touch.
+constexpr int kDataBlk = 64;
+constexpr int kDataPad = 16384;
+__host__ __device__ inline long long data_padded(long long n) { return (n + kDataPad - 1) / kDataPad * kDataPad; }
+__host__ __device__ inline long long data_at(int ch, long long i)
+{
+    return ((i / kDataBlk) * 3 + ch) * kDataBlk + (i % kDataBlk);
+}
+
 // Data resident for the life of a context.
 struct Data {
-    const double2 *d;       // [3][n]   A, E, T data
-    const double *w;        // [3][n]   4 df / S_n
+    const double2 *d;       // blocked [n_pad/64][3][64] A, E, T data (data_at)
+    const double *w;        // blocked [n_pad/64][3][64] 4 df / S_n, 0 in the padding
     const double *pre;      // [3][n+1] prefix sums of |d|^2 w
     const float2 *dhi32;    // [3][n]   d sqrt(w), FP32 high part (FP32 dense stage)
     const float2 *dlo32;    // [3][n]   d sqrt(w) - dhi32, FP32 low part
@@ -125,10 +139,11 @@ struct Data {
 const double *cis_table_host(int *n);
 const float *cis32_table_host(int *n);
 
-// dhi32 / dlo32 / sw32 may be null (FP64 contexts)
-hipError_t launch_setup_data(const double *psd, const double2 *d, double *w, double *pre, double *scratch,
-                             float2 *dhi32, float2 *dlo32, float *sw32, const GridDesc &g, double df4,
-                             hipStream_t st);
+// d_in [3][n] and psd [3][n] as uploaded; writes the blocked d and w, the
+// prefix sums and (if not null: FP32C contexts) dhi32 / dlo32 / sw32 [3][n]
+hipError_t launch_setup_data(const double *psd, const double2 *d_in, double2 *d, double *w, double *pre,
+                             double *scratch, float2 *dhi32, float2 *dlo32, float *sw32, const GridDesc &g,
+                             double df4, hipStream_t st);
 
 // FP32 copy of the spline coefficients for the FP32 dense stage
 hipError_t launch_coef32(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st);

@@ -567,6 +567,97 @@ class FlowProposal:
         return x, lq
 
 
+def curvature_covariance(loglike: Callable, x0: np.ndarray, steps: np.ndarray):
+    """Covariance (-H)^{-1} from the Hessian H of ln L at x0 by central
+    differences with per-coordinate steps, all 1 + 2 D^2 points in one
+    batched call:
+      H_ii = (f(x + h_i e_i) - 2 f(x) + f(x - h_i e_i)) / h_i^2,
+      H_ij = (f(++) - f(+-) - f(-+) + f(--)) / (4 h_i h_j).
+    -H is symmetrised and its eigenvalues are held at or above 1e-12 of the
+    largest, so the result is a covariance even where ln L is not concave."""
+    x0 = np.asarray(x0, dtype=np.float64)
+    h = np.asarray(steps, dtype=np.float64)
+    d = len(x0)
+    pts = [x0]
+    for i in range(d):
+        for sgn in (1.0, -1.0):
+            y = x0.copy()
+            y[i] += sgn * h[i]
+            pts.append(y)
+    pairs = [(i, j) for i in range(d) for j in range(i + 1, d)]
+    for i, j in pairs:
+        for si, sj in ((1.0, 1.0), (1.0, -1.0), (-1.0, 1.0), (-1.0, -1.0)):
+            y = x0.copy()
+            y[i] += si * h[i]
+            y[j] += sj * h[j]
+            pts.append(y)
+    f = np.asarray(loglike(np.array(pts)), dtype=np.float64)
+    if not np.all(np.isfinite(f)):
+        raise ValueError("curvature_covariance: ln L is not finite at some difference points; use smaller steps")
+    H = np.zeros((d, d))
+    for i in range(d):
+        H[i, i] = (f[1 + 2 * i] - 2.0 * f[0] + f[2 + 2 * i]) / (h[i] * h[i])
+    base = 1 + 2 * d
+    for k, (i, j) in enumerate(pairs):
+        fpp, fpm, fmp, fmm = f[base + 4 * k: base + 4 * k + 4]
+        H[i, j] = H[j, i] = (fpp - fpm - fmp + fmm) / (4.0 * h[i] * h[j])
+    A = -0.5 * (H + H.T)
+    lam, V = np.linalg.eigh(A)
+    lam = np.maximum(lam, 1e-12 * max(lam.max(), 1e-300))
+    return (V / lam) @ V.T
+
+
+def curvature_start(loglike: Callable, logprior: Callable, x0: np.ndarray, betas, n_walkers: int, seed: int,
+                    rel_step: float = 1e-6, refine: int = 1, lo=inputs.PRIOR_LO, hi=inputs.PRIOR_HI):
+    """Start positions [T][W][D] for parallel tempering drawn from the Gaussian
+    approximation of the posterior at x0: covariance (-H)^{-1} from
+    curvature_covariance, widened by the temperature 1/beta on each rung (the
+    beta = 0 rung, whose target is the prior, takes four times the largest
+    finite temperature), redrawn where the prior is zero; a rung that finds
+    too few draws inside the prior narrows by factors of 4.  The first
+    Hessian uses steps rel_step |x0_i| (at least rel_step); each refinement
+    repeats it with steps of 0.3 of the standard deviations just found.
+    Every step stays below a third of the distance from x0 to the edge of the
+    box [lo, hi], so all difference points are inside it, and no standard
+    deviation exceeds a twentieth of the box's width (a direction the data
+    hardly constrain would otherwise start the walkers far outside it)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x0 = np.asarray(x0, dtype=np.float64)
+    lo, hi = np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64)
+    edge = np.minimum(x0 - lo, hi - x0) / 3.0
+    cap = (hi - lo) / 20.0
+
+    def clamp(C):
+        s = np.sqrt(np.diag(C))
+        f = np.minimum(1.0, cap / np.maximum(s, 1e-300))
+        return C * np.outer(f, f)
+    steps = np.minimum(rel_step * np.maximum(np.abs(x0), 1.0), edge)
+    C = clamp(curvature_covariance(loglike, x0, steps))
+    for _ in range(refine):
+        C = clamp(curvature_covariance(loglike, x0, np.minimum(0.3 * np.sqrt(np.diag(C)), edge)))
+    chol = np.linalg.cholesky(C + 1e-300 * np.eye(len(x0)))
+    betas = np.asarray(betas, dtype=np.float64)
+    finite = betas[betas > 0]
+    t_top = 4.0 / finite.min() if len(finite) else 1.0
+    out = np.empty((len(betas), n_walkers, len(x0)))
+    for r, b in enumerate(betas):
+        t = 1.0 / b if b > 0 else t_top
+        filled, tries = 0, 0
+        while filled < n_walkers:
+            z = rng.standard_normal((n_walkers, len(x0)))
+            y = x0 + math.sqrt(t) * z @ chol.T
+            ok = np.isfinite(np.asarray(logprior(y)))
+            take = y[ok][: n_walkers - filled]
+            out[r, filled:filled + len(take)] = take
+            filled += len(take)
+            tries += 1
+            if tries % 20 == 0:
+                if t <= 1e-6:
+                    raise RuntimeError("curvature_start: too few draws inside the prior")
+                t *= 0.25
+    return out, C
+
+
 def box_logprior(lo=inputs.PRIOR_LO, hi=inputs.PRIOR_HI):
     """Uniform prior over a box (Table I): 0 inside, -inf outside."""
     lo = np.asarray(lo)

@@ -7,14 +7,20 @@ the thinned burn-in chain (training time charged to it) and runs N steps of
 stretch + independence proposals.  ESS uses the Sokal-window integrated time
 of Sec. III.C on the N steps of each arm.
 
-1. A curved ('banana') 11-D density with a cheap analytic log-likelihood:
-   the flow must raise ESS per likelihood evaluation, the quantity that
-   becomes ESS/s when the likelihood dominates the cost.
-2. The batched MBHB likelihood of this library on the small grid: the flow
-   must raise ESS per second of wall time, training and flow overhead
-   included.
-Both arms must agree on the posterior: means within 4.5 combined Monte Carlo
-standard errors (11 parameters) and standard deviations within 10 %.
+1. A curved ('banana') 11-D density with a cheap analytic log-likelihood,
+   one rung, a = 2: the flow must raise ESS per likelihood evaluation, the
+   quantity that becomes ESS/s when the likelihood dominates the cost; both
+   arms must agree within 4.5 combined walker-averaged Monte Carlo standard
+   errors and 10 % in standard deviation.
+2. The batched MBHB likelihood of this library on the small grid with the
+   paper's sampler settings: parallel tempering over 4 rungs of the paper's
+   ladder, stretch scale a = 1.15, chains started from the Gaussian
+   approximation of the posterior at the injection.  The flow must raise the
+   effective samples of the ensemble mean (batch means) per second of wall
+   time, training and flow overhead included, at equal posterior accuracy:
+   every mean within 3 combined batch-means standard errors of the ensemble
+   mean, every standard deviation within 5 %.  The walker-averaged ESS of
+   Sec. III.C is printed beside it.
 """
 import time
 
@@ -84,19 +90,64 @@ def test_flow_raises_ess_per_evaluation_on_a_curved_density(gpu):
     assert r["ess_f"] > 5 * r["ess_b"]          # the same number of likelihood evaluations
 
 
+def _compare_pt(loglike, logprior, x0, betas, burn, steps, fit_kwargs, a=1.15, p_flow=0.8, thin=5):
+    """The protocol above with parallel tempering: x0[T][W][D]."""
+    nt, nw = x0.shape[0], x0.shape[1]
+    base = S.PTSampler(loglike, logprior, betas, nw, DIM, a=a, seed=5)
+    base.initialize(x0)
+    warm = base.run(burn)
+    start = base.state.x.copy()
+    t = time.perf_counter()
+    ch_b = base.run(steps)
+    wall_b = time.perf_counter() - t
+    t = time.perf_counter()
+    prop = S.FlowProposal(DIM, max_batch=16384, seed=55)
+    prop.fit(warm[len(warm) // 2:][::thin].reshape(-1, DIM), **fit_kwargs)
+    fl = S.PTSampler(loglike, logprior, betas, nw, DIM, a=a, seed=55, proposal=prop, p_flow=p_flow)
+    fl.initialize(start)
+    ch_f = fl.run(steps)
+    wall_f = time.perf_counter() - t
+    ess_b, tau_b, _ = S.ess(ch_b)
+    ess_f, tau_f, _ = S.ess(ch_f)
+    acc = fl.state.flow_accepted / max(1, fl.state.flow_proposed)
+    a1, a2 = ch_b.reshape(-1, DIM), ch_f.reshape(-1, DIM)
+    se_b, se_f = S.batch_means_se(ch_b), S.batch_means_se(ch_f)
+    z = float(np.max(np.abs(a1.mean(0) - a2.mean(0)) / np.sqrt(se_b ** 2 + se_f ** 2)))
+    sd = float(np.max(np.abs(a2.std(0) / a1.std(0) - 1)))
+    bm_b = float(np.min(a1.var(0) / se_b ** 2))
+    bm_f = float(np.min(a2.var(0) / se_f ** 2))
+    print(f"PT {nt} x {nw}, a = {a}: stretch only: tau {tau_b:.1f} ESS {ess_b:.0f} (batch means {bm_b:.0f}) "
+          f"wall {wall_b:.2f} s -> {ess_b / wall_b:.1f} ESS/s; acceptance T=1 "
+          f"{base.state.accepted[0] / max(1, base.state.proposed[0]):.3f}", flush=True)
+    print(f"stretch+flow: tau {tau_f:.1f} ESS {ess_f:.0f} (batch means {bm_f:.0f}) wall {wall_f:.2f} s (training "
+          f"{prop.train_seconds:.2f} s) -> {ess_f / wall_f:.1f} ESS/s; flow acceptance {acc:.2f}; arms agree: "
+          f"z_bm {z:.2f}, sd {sd:.3f}", flush=True)
+    prop.flow.close()
+    return dict(ess_b=ess_b, ess_f=ess_f, wall_b=wall_b, wall_f=wall_f, acc=acc, z=z, sd=sd, bm_b=bm_b, bm_f=bm_f,
+                tau_b=tau_b, tau_f=tau_f, n=steps)
+
+
 def test_flow_raises_ess_per_second_on_the_mbhb_likelihood(gpu, oracle):
-    """Posterior sampling on the small grid through the GPU likelihood."""
+    """Posterior sampling on the small grid through the GPU likelihood, with
+    the paper's stretch scale and a tempered ladder."""
     from paper_2005_01827_amd import mbh
-    w = inputs.small_config(64, seed=21)
+    w = inputs.small_config(1, seed=21)
     g = w.grid
     psd = inputs.psd_aet(g.freqs)
     d = oracle.template(w.injection, g, w.modes, w.ns, w.t0) + inputs.noise(g, psd, 22)
-    L = mbh.Likelihood(g, d, psd, w.modes, w.ns, w.t0, max_batch=64)
+    nt, nw = 4, 128
+    betas = S.ladder(nt)
+    L = mbh.Likelihood(g, d, psd, w.modes, w.ns, w.t0, max_batch=nt * nw)
     try:
         ll = S.gpu_loglike(L)
-        x0 = inputs.to_sampling(inputs.ball(w.injection, 64, 2e-5, 23))[None]
-        r = _compare(ll, S.box_logprior(), x0, 3000, 4000, dict(steps=600, lr=2e-3, batch=4096, seed=55))
+        lp = S.box_logprior()
+        x0, _ = S.curvature_start(ll, lp, inputs.to_sampling(w.injection), betas, nw, seed=23)
+        r = _compare_pt(ll, lp, x0, betas, 2000, 8000, dict(steps=600, lr=2e-3, batch=4096, seed=55))
     finally:
         L.close()
-    assert r["z"] < 4.5 and r["sd"] < 0.1
-    assert r["ess_f"] / r["wall_f"] > 1.5 * r["ess_b"] / r["wall_b"]
+    assert r["z"] < 3.0 and r["sd"] < 0.05
+    # ESS of the ensemble mean by batch means: the walker-averaged estimator
+    # of Sec. III.C subtracts each walker's own mean and misses that the
+    # stretch move's walkers move together (it reports about 40 times the
+    # batch-means ESS on the stretch arm here, 5 times on the flow arm)
+    assert r["bm_f"] / r["wall_f"] > 1.5 * r["bm_b"] / r["wall_b"]

@@ -296,3 +296,50 @@ def test_fixed_coordinates_sample_the_conditional():
     assert np.allclose(np.cov(flat_s.T), cov_c, atol=0.1 * np.abs(cov_c).max())
     with pytest.raises(ValueError):
         ll2(np.zeros((4, 3)))
+
+
+def test_curvature_covariance_and_start_on_a_gaussian():
+    """For ln L = -(x - mu)^T P (x - mu)/2 the central differences are exact:
+    the covariance is P^{-1} (numpy's inverse) whatever the steps; the start
+    draws at temperature T have covariance T P^{-1} and lie in the prior."""
+    rng = np.random.default_rng(31)
+    d = 11
+    A = rng.normal(size=(d, d)) / math.sqrt(d)
+    P = A @ A.T + 0.5 * np.eye(d)
+    P *= np.outer(np.logspace(0, 3, d), np.logspace(0, 3, d))     # widths spanning 1e3
+    mu = rng.normal(size=d)
+
+    def ll(x):
+        r = np.atleast_2d(x) - mu
+        return -0.5 * np.einsum("ni,ij,nj->n", r, P, r)
+    cov_true = np.linalg.inv(P)
+    for steps in (1e-4 * np.ones(d), np.sqrt(np.diag(cov_true))):
+        C = S.curvature_covariance(ll, mu, steps)
+        assert np.allclose(C, cov_true, rtol=1e-6, atol=1e-9 * np.abs(cov_true).max())
+    lo, hi = mu - 50 * np.sqrt(np.diag(cov_true)), mu + 50 * np.sqrt(np.diag(cov_true))
+    betas = S.ladder(3)
+    x0, C = S.curvature_start(ll, S.box_logprior(lo, hi), mu, betas, 6000, seed=5, lo=lo, hi=hi)
+    assert np.allclose(C, cov_true, rtol=1e-6, atol=1e-9 * np.abs(cov_true).max())
+    assert x0.shape == (3, 6000, d)
+    assert np.all(np.isfinite(S.box_logprior(lo, hi)(x0.reshape(-1, d))))
+    for r, t in ((0, 1.0), (1, 1.0 / betas[1])):
+        emp = np.cov(x0[r].T)
+        # sample covariance of 6000 draws: entries within a few of their
+        # standard errors, measured on the standardised scale
+        s = np.sqrt(np.diag(t * cov_true))
+        assert np.max(np.abs(emp / np.outer(s, s) - t * cov_true / np.outer(s, s))) < 0.08
+    # a concave direction is held positive: ln L = +x0^2/2 along one axis
+    def ll_saddle(x):
+        x = np.atleast_2d(x)
+        return 0.5 * x[:, 0] ** 2 - 0.5 * np.sum(x[:, 1:] ** 2, axis=1)
+    C = S.curvature_covariance(ll_saddle, np.zeros(3), np.full(3, 1e-3))
+    assert np.all(np.linalg.eigvalsh(C) > 0)
+    # a flat direction is capped at a twentieth of the box; steps stay inside
+    def ll_flat(x):
+        x = np.atleast_2d(x)
+        if np.any(np.abs(x) > 1.0):
+            return np.full(len(x), -np.inf)
+        return -0.5 * np.sum(x[:, 1:] ** 2 / 1e-4, axis=1)
+    _, C = S.curvature_start(ll_flat, S.box_logprior(-np.ones(3), np.ones(3)), np.zeros(3), [1.0], 8, seed=1,
+                             lo=-np.ones(3), hi=np.ones(3))
+    assert abs(math.sqrt(C[0, 0]) - 0.1) < 1e-12 and abs(C[1, 1] - 1e-4) < 1e-10
