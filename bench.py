@@ -76,9 +76,9 @@ def parse():
                          "it: latency (one walker, T_obs = 2^22 s), uneven (2048 uneven walkers), precision "
                          "(FP32C against FP64 at three SNRs), sampler (ESS/s, learned proposal vs stretch); "
                          "'none' for the throughput line alone")
-    ap.add_argument("--extra-sampler-seconds", type=float, default=45.0,
+    ap.add_argument("--extra-sampler-seconds", type=float, default=60.0,
                     help="seconds per arm of the bounded ESS/s comparison in the throughput line")
-    ap.add_argument("--extra-sampler-burn", type=float, default=60.0,
+    ap.add_argument("--extra-sampler-burn", type=float, default=120.0,
                     help="seconds of the shared stretch-only burn-in of that comparison")
     ap.add_argument("--extra-sampler-init", default="curvature", choices=["curvature", "ball"],
                     help="start of its chains (as --sampler-init)")
@@ -766,7 +766,10 @@ def extra_sampler(args, w, data):
             "ess_per_s_gain": rep["ess_per_s_gain"], "ess_per_s_gain_batch_means": rep["ess_per_s_gain_batch_means"],
             "equal_accuracy": rep["accuracy"]["equal"],
             "max_mean_diff_in_batch_means_se": rep["accuracy"]["max_mean_diff_in_batch_means_se"],
-            "max_sd_rel_diff": rep["accuracy"]["max_sd_rel_diff"]}
+            "max_sd_rel_diff": rep["accuracy"]["max_sd_rel_diff"],
+            "mean_diff_in_batch_means_se": rep["accuracy"]["mean_diff_in_batch_means_se"],
+            "stretch_arm_half_vs_half_in_batch_means_se": rep["accuracy"]["stretch_arm_half_vs_half_in_batch_means_se"],
+            "flow_arm_half_vs_half_in_batch_means_se": rep["accuracy"]["flow_arm_half_vs_half_in_batch_means_se"]}
 
 
 def cpu_baseline(args, O, w, data, psd, lnl, gpu_evals_per_s):

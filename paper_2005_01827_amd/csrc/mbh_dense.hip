@@ -345,6 +345,34 @@ struct DenseArgs {
 
 __device__ __forceinline__ int uni_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Interval of dense bin k among the knot bins kb[0..ns-1] of one (walker,
+// mode): the largest iv in [c, ns-2] with kb[iv] <= k, for kb[c] <= k, and
+// nb = kb[iv + 1].  win holds kb[min(c + 1 + lane, ns - 1)], the 64 knot bins
+// after the step's first interval, one per lane: a binary search over that
+// window by shuffles (seven probes, no memory access) replaces a walk with
+// one dependent load per knot, which dominated steps that cross many knots.
+// Every lane of the wavefront must take part (the shuffles read other
+// lanes); beyond the window (more than 64 knots in one step) or at the last
+// interval the walk over kb finishes the search.
+__device__ __forceinline__ int lane_interval(const int *kb, int ns, int c, int win, int k, int &nb)
+{
+    int t = -1;   // largest t with win[t] <= k, -1 if none
+#pragma unroll
+    for (int s2 = 64; s2 >= 1; s2 >>= 1) {
+        const int p = t + s2;
+        const int v = __shfl(win, p < 63 ? p : 63, 64);
+        if (p <= 63 && v <= k) t = p;
+    }
+    int iv = c + 1 + t;
+    nb = __shfl(win, t < 62 ? t + 1 : 63, 64);
+    if (t == 63 || iv > ns - 2) {
+        iv = min(iv, ns - 2);
+        while (iv < ns - 2 && kb[iv + 1] <= k) ++iv;
+        nb = kb[iv + 1];
+    }
+    return iv;
+}
+
 // e^{i phi} = e^{i q pi/512} e^{i r}.  t = phi 512/pi is rounded to the
 // integer q by adding and subtracting 1.5 2^52 (exact for |t| < 2^51), which
 // leaves q mod 2^32 in the low word of the sum; r = phi - q pi/512 with a
@@ -857,13 +885,14 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
                 } else {
                     // FP32 stage: per-lane evaluation in place (deferring did
                     // not pay there)
+                    const int win = a.kbin[kbo + min(cur[m] + 1 + lane, ns - 1)];
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
+                        int nb;
+                        const int iv = lane_interval(a.kbin + kbo, ns, cur[m], win, k[b], nb);
                         if (k[b] < mlo[m] || k[b] > mhi[m]) continue;
-                        int iv = cur[m];
-                        while (iv < ns - 2 && a.kbin[kbo + iv + 1] <= k[b]) ++iv;
                         const size_t c0 = (size_t)(ivo + iv) * kCoefPerIv;
-                        const double xc = (double)a.kbin[kbo + iv + 1] * a.df;
+                        const double xc = (double)nb * a.df;
                         mode_bin32<const double *, const float *>(K, Kf, a.coef + c0, a.coef32 + c0, f[b] - xc,
                                                                   hr32[b], hi32[b]);
                     }
@@ -880,13 +909,14 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
                 const int ivo = kbo - wm;
                 const ModeBand mb = a.band[wm];
                 const int c = uni_i(xcur[wave][m]);
+                const int win = a.kbin[kbo + min(c + 1 + lane, ns - 1)];
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
+                    int nb;
+                    const int iv = lane_interval(a.kbin + kbo, ns, c, win, k[b], nb);
                     if (k[b] < mb.klo || k[b] > mb.khi) continue;
-                    int iv = c;
-                    while (iv < ns - 2 && a.kbin[kbo + iv + 1] <= k[b]) ++iv;
                     const size_t c0 = (size_t)(ivo + iv) * kCoefPerIv;
-                    const double xc = (double)a.kbin[kbo + iv + 1] * a.df;
+                    const double xc = (double)nb * a.df;
                     mode_bin<const double *>(K, a.coef + c0, f[b] - xc, hr[b], hi[b]);
                 }
             }

@@ -797,10 +797,13 @@ def ess_comparison(loglike: Callable, logprior: Callable, x0: np.ndarray, betas,
     se_bm = np.sqrt(batch_means_se(ch_plain) ** 2 + batch_means_se(ch_flow) ** 2)
     h = len(ch_plain) // 2
     se_drift = np.sqrt(batch_means_se(ch_plain[:h], 10) ** 2 + batch_means_se(ch_plain[h:], 10) ** 2)
+    hf = len(ch_flow) // 2
+    se_drift_f = np.sqrt(batch_means_se(ch_flow[:hf], 10) ** 2 + batch_means_se(ch_flow[hf:], 10) ** 2)
     with np.errstate(divide="ignore", invalid="ignore"):
         z = np.abs(a1.mean(0) - a2.mean(0)) / se
         z_bm = np.abs(a1.mean(0) - a2.mean(0)) / se_bm
         z_drift = np.abs(ch_plain[:h].reshape(-1, dim).mean(0) - ch_plain[h:].reshape(-1, dim).mean(0)) / se_drift
+        z_drift_f = np.abs(ch_flow[:hf].reshape(-1, dim).mean(0) - ch_flow[hf:].reshape(-1, dim).mean(0)) / se_drift_f
         zmax = float(np.nanmax(z))
         sd_rel = float(np.nanmax(np.abs(a2.std(0) / a1.std(0) - 1)))
     zmax_bm = float(np.nanmax(z_bm))
@@ -812,7 +815,8 @@ def ess_comparison(loglike: Callable, logprior: Callable, x0: np.ndarray, betas,
                        "equal": bool(zmax_bm < 3 and sd_rel < 0.05),
                        "mean_diff_in_se": [round(float(v), 2) for v in z],
                        "mean_diff_in_batch_means_se": [round(float(v), 2) for v in z_bm],
-                       "stretch_arm_half_vs_half_in_batch_means_se": [round(float(v), 2) for v in z_drift]}
+                       "stretch_arm_half_vs_half_in_batch_means_se": [round(float(v), 2) for v in z_drift],
+                       "flow_arm_half_vs_half_in_batch_means_se": [round(float(v), 2) for v in z_drift_f]}
     if keep_chains:
         out["chains"] = (ch_plain, ch_flow)
     out["ess_per_s_gain"] = round(out["stretch_flow"]["ess_per_s"] / max(out["stretch"]["ess_per_s"], 1e-12), 3)
