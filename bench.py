@@ -756,7 +756,8 @@ def extra_sampler(args, w, data):
     finally:
         L.close()
     keep = ("steps", "wall_s", "tau", "ess", "ess_per_s", "ess_batch_means", "ess_batch_means_per_s",
-            "chain_over_50_tau", "acceptance_per_rung", "swap_rate", "flow_acceptance")
+            "chain_over_50_tau", "ensemble_tau_batch_means", "chain_over_50_ensemble_tau", "acceptance_per_rung",
+            "swap_rate", "flow_acceptance")
     return {"rungs": nt, "walkers_per_rung": nw, "stretch_a": 1.15, "init": args.extra_sampler_init,
             "init_ball_rel": args.extra_sampler_init_rel,
             "burn_in": rep["burn_in"],
@@ -765,6 +766,7 @@ def extra_sampler(args, w, data):
             "stretch_flow": dict({k: rep["stretch_flow"][k] for k in keep}, train_s=rep["stretch_flow"]["train_s"]),
             "ess_per_s_gain": rep["ess_per_s_gain"], "ess_per_s_gain_batch_means": rep["ess_per_s_gain_batch_means"],
             "equal_accuracy": rep["accuracy"]["equal"],
+            "runs_over_50_ensemble_tau": rep["accuracy"]["runs_over_50_ensemble_tau"],
             "max_mean_diff_in_batch_means_se": rep["accuracy"]["max_mean_diff_in_batch_means_se"],
             "max_sd_rel_diff": rep["accuracy"]["max_sd_rel_diff"],
             "mean_diff_in_batch_means_se": rep["accuracy"]["mean_diff_in_batch_means_se"],

@@ -111,7 +111,10 @@ mbh_status mbh_response(mbh_ctx *ctx, int B, void *stream);
 mbh_status mbh_interp_and_inner(mbh_ctx *ctx, int B, double *out7_dev, void *stream);
 
 /* The three stages above in one call, launched as one captured HIP graph per
- * (B, stream) after the first call: logL_dev[B] (device) receives ln L.  On
+ * batch size after the first call: logL_dev[B] (device) receives ln L.  The
+ * graph reads params_dev and writes logL_dev directly (its first and last
+ * kernels are pointed at the caller's buffers before each launch), so both
+ * buffers must stay valid until the work on 'stream' has completed.  On
  * the FP64 path the dense stage accumulates only the residual sums here (ln L
  * needs nothing else), so ln L is bitwise the value mbh_interp_and_inner
  * returns. */

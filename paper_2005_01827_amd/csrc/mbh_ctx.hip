@@ -44,7 +44,17 @@ struct mbh_ctx {
     double *params = nullptr;     // [max_batch][11] staging for graph launches
     double *logL = nullptr;       // [max_batch]
     std::vector<void *> allocs;
-    std::map<int, hipGraphExec_t> graphs;   // per batch size
+    // one captured likelihood graph per batch size; the nodes of its first
+    // kernel (reads the walker parameters) and last kernel (writes ln L) are
+    // pointed at the caller's buffers before each launch
+    struct GraphEntry {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipGraphNode_t src = nullptr, red = nullptr;
+        const double *params = nullptr;   // buffers the exec's nodes use now
+        double *logL = nullptr;
+    };
+    std::map<int, GraphEntry> graphs;
     hipGraph_t graph_tmp = nullptr;
     std::string err;
     // stage order of the staged calls: the last completed stage over the
@@ -111,7 +121,10 @@ void drop_events(mbh_ctx *c)
 
 void drop_graphs(mbh_ctx *c)
 {
-    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : c->graphs) {
+        (void)hipGraphExecDestroy(kv.second.exec);
+        (void)hipGraphDestroy(kv.second.graph);
+    }
     c->graphs.clear();
 }
 
@@ -168,6 +181,36 @@ mbh_status enqueue_all(mbh_ctx *c, const double *params, int B, double *out7, do
         return hip_fail(c, e, "dense");
     if ((e = launch_reduce(B, c->g, c->wk, data_of(c), out7, logL, st)) != hipSuccess) return hip_fail(c, e, "reduce");
     return MBH_OK;
+}
+
+// The kernel node of 'fn' in a captured graph (nullptr if absent).
+hipGraphNode_t find_kernel_node(hipGraph_t graph, const void *fn)
+{
+    size_t nn = 0;
+    if (hipGraphGetNodes(graph, nullptr, &nn) != hipSuccess || nn == 0) return nullptr;
+    std::vector<hipGraphNode_t> nodes(nn);
+    if (hipGraphGetNodes(graph, nodes.data(), &nn) != hipSuccess) return nullptr;
+    for (hipGraphNode_t n : nodes) {
+        hipGraphNodeType t;
+        if (hipGraphNodeGetType(n, &t) != hipSuccess || t != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp;
+        if (hipGraphKernelNodeGetParams(n, &kp) != hipSuccess) continue;
+        if (kp.func == fn && kp.kernelParams != nullptr) return n;
+    }
+    return nullptr;
+}
+
+// Point argument 'arg' (a device pointer) of kernel node 'node' of 'exec' at p;
+// the other arguments keep their captured values.
+hipError_t retarget(hipGraphExec_t exec, hipGraphNode_t node, int arg, int nargs, const void *p)
+{
+    hipKernelNodeParams kp;
+    hipError_t e = hipGraphKernelNodeGetParams(node, &kp);
+    if (e != hipSuccess) return e;
+    std::vector<void *> args(kp.kernelParams, kp.kernelParams + nargs);
+    args[arg] = &p;
+    kp.kernelParams = args.data();
+    return hipGraphExecKernelNodeSetParams(exec, node, &kp);
 }
 
 // Device address of 'scratch' on each device, taken once per device with
@@ -427,8 +470,7 @@ mbh_status mbh_loglike_batch(mbh_ctx *ctx, const double *params_dev, int B, doub
     if (!params_dev || !logL_dev) return fail(ctx, MBH_EINVAL, "mbh: null params or logL");
     set_stage(ctx, 0, 0);
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(ctx->params, params_dev, sizeof(double) * 11 * B, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "params copy");
+    hipError_t e;
     if (ctx->timing) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(ctx, e, "event create");
@@ -437,17 +479,16 @@ mbh_status mbh_loglike_batch(mbh_ctx *ctx, const double *params_dev, int B, doub
             return hip_fail(ctx, e, "event create");
         }
         ctx->events.emplace_back(e0, e1);
-        st = enqueue_all(ctx, ctx->params, B, ctx->wk.out7, ctx->logL, s, e0, e1);
+        st = enqueue_all(ctx, params_dev, B, ctx->wk.out7, logL_dev, s, e0, e1);
         if (st != MBH_OK) return st;
-        e = hipMemcpyAsync(logL_dev, ctx->logL, sizeof(double) * B, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return hip_fail(ctx, e, "logL copy");
         set_stage(ctx, 2, B);
         return MBH_OK;
     }
     auto it = ctx->graphs.find(B);
     if (it == ctx->graphs.end()) {
         // capture the fixed sequence of kernels for this batch size on a
-        // private stream, then instantiate it
+        // private stream (with the context's staging buffers), then
+        // instantiate it and find the two nodes that touch caller memory
         hipStream_t cap;
         if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return hip_fail(ctx, e, "stream");
         hipGraph_t graph = nullptr;
@@ -464,15 +505,39 @@ mbh_status mbh_loglike_batch(mbh_ctx *ctx, const double *params_dev, int B, doub
             if (graph) (void)hipGraphDestroy(graph);
             return st;
         }
-        hipGraphExec_t exec = nullptr;
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) return hip_fail(ctx, e, "graph instantiate");
-        it = ctx->graphs.emplace(B, exec).first;
+        mbh_ctx::GraphEntry ge;
+        ge.graph = graph;
+        ge.src = find_kernel_node(graph, source_kernel());
+        ge.red = find_kernel_node(graph, reduce_kernel());
+        ge.params = ctx->params;
+        ge.logL = ctx->logL;
+        e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(ctx, e, "graph instantiate");
+        }
+        it = ctx->graphs.emplace(B, ge).first;
     }
-    if ((e = hipGraphLaunch(it->second, s)) != hipSuccess) return hip_fail(ctx, e, "graph launch");
-    e = hipMemcpyAsync(logL_dev, ctx->logL, sizeof(double) * B, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "logL copy");
+    mbh_ctx::GraphEntry &ge = it->second;
+    // the first kernel reads params (argument 0 of 4), the last writes ln L
+    // (argument 8 of 9); where a node was not found, the parameters and ln L
+    // go through the context's staging buffers instead
+    const bool direct_in = ge.src != nullptr, direct_out = ge.red != nullptr;
+    if (direct_in && ge.params != params_dev) {
+        if ((e = retarget(ge.exec, ge.src, 0, 4, params_dev)) != hipSuccess) return hip_fail(ctx, e, "graph node update");
+        ge.params = params_dev;
+    }
+    if (direct_out && ge.logL != logL_dev) {
+        if ((e = retarget(ge.exec, ge.red, 8, 9, logL_dev)) != hipSuccess) return hip_fail(ctx, e, "graph node update");
+        ge.logL = logL_dev;
+    }
+    if (!direct_in &&
+        (e = hipMemcpyAsync(ctx->params, params_dev, sizeof(double) * 11 * B, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return hip_fail(ctx, e, "params copy");
+    if ((e = hipGraphLaunch(ge.exec, s)) != hipSuccess) return hip_fail(ctx, e, "graph launch");
+    if (!direct_out &&
+        (e = hipMemcpyAsync(logL_dev, ctx->logL, sizeof(double) * B, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+        return hip_fail(ctx, e, "logL copy");
     set_stage(ctx, 2, B);
     return MBH_OK;
 }

@@ -737,8 +737,12 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
     // (one_per_walker), or the next free item from a counter (tickets): a
     // workgroup that finishes early takes more, and workgroups running
     // together stay on neighbouring items of the list.  The next ticket is
-    // requested when an item starts and published at its last barrier.
-    __shared__ int next_item;
+    // taken when an item starts and read by every thread after the item's
+    // last barrier, through two LDS slots used in turn (a slot is rewritten
+    // only two items later, after a barrier that every reader has passed),
+    // so no register holds it across the item.
+    __shared__ int next_item[2];
+    int par = 0;
     const bool tickets = !kWriteH && a.use_ticket && !a.one_per_walker;
     int item = blockIdx.x, end = total, step = gridDim.x;
     if (a.one_per_walker) {
@@ -747,17 +751,22 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
         step = 1;
     }
     if (tickets) {
-        if (threadIdx.x == 0) next_item = atomicAdd(a.ticket, 1);
+        if (threadIdx.x == 0) next_item[0] = atomicAdd(a.ticket, 1);
         __syncthreads();
-        item = uni_i(next_item);
+        item = uni_i(next_item[0]);
     }
     while (item < end) {
-        int ticket_next = 0;
-        if (tickets && threadIdx.x == 0) ticket_next = atomicAdd(a.ticket, 1);
+        if (tickets && threadIdx.x == 0) next_item[par ^ 1] = atomicAdd(a.ticket, 1);
+        // item values are wave-uniform: held in scalar registers, so that
+        // none occupies a vector register across the item
         const int wk = a.one_per_walker ? (int)blockIdx.x : uni_i(a.item_w[item]);
-        const WalkerBand wb = a.wband[wk];
-        const int tile = a.one_per_walker ? wb.tile_lo + (item - a.wbase[wk]) : uni_i(a.item_t[item]);
-        const int slot = a.wbase[wk] + (tile - wb.tile_lo);
+        WalkerBand wb = a.wband[wk];
+        wb.klo = uni_i(wb.klo);
+        wb.khi = uni_i(wb.khi);
+        wb.tile_lo = uni_i(wb.tile_lo);
+        const int base = uni_i(a.wbase[wk]);
+        const int tile = a.one_per_walker ? wb.tile_lo + (item - base) : uni_i(a.item_t[item]);
+        const int slot = uni_i(base + (tile - wb.tile_lo));
         const int kw = uni_i(a.k0 + tile * a.tile_bins + wave * (64 * a.steps));
         const int kwl = kw + 64 * a.steps - 1;
 
@@ -1012,9 +1021,13 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
             for (int wv = 0; wv < kDenseThreads / 64; ++wv) s += red[wv][threadIdx.x];
             a.partial[(size_t)slot * kPartials + threadIdx.x] = s;
         }
-        if (tickets && threadIdx.x == 0) next_item = ticket_next;
         __syncthreads();
-        item = tickets ? uni_i(next_item) : item + step;
+        if (tickets) {
+            par ^= 1;
+            item = uni_i(next_item[par]);
+        } else {
+            item += step;
+        }
     }
 }
 
@@ -1231,6 +1244,8 @@ hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &w
     if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
     return hipGetLastError();
 }
+
+const void *reduce_kernel() { return reinterpret_cast<const void *>(&k_reduce); }
 
 hipError_t launch_reduce(int B, const GridDesc &g, const Work &wk, const Data &dt, double *out7, double *logL,
                          hipStream_t st)

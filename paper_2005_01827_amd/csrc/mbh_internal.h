@@ -178,6 +178,13 @@ hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &w
 hipError_t launch_reduce(int B, const GridDesc &g, const Work &wk, const Data &dt, double *out7,
                          double *logL, hipStream_t st);
 
+// Host handles of the first and last kernels of a likelihood sweep (the one
+// that reads the walker parameters, the one that writes ln L), by which the
+// context finds their nodes in a captured graph and points them at the
+// caller's buffers for each launch.
+const void *source_kernel();
+const void *reduce_kernel();
+
 hipError_t launch_template(const Modes &md, const GridDesc &g, const Work &wk, double2 *h, hipStream_t st);
 
 }  // namespace mbh

@@ -397,6 +397,8 @@ __global__ void k_knots(int B, Modes md, GridDesc g, const Source *__restrict__ 
 
 }  // namespace
 
+const void *source_kernel() { return reinterpret_cast<const void *>(&k_source); }
+
 hipError_t launch_waveform(const double *params, int B, const Modes &md, const GridDesc &g, const Work &wk,
                            hipStream_t st)
 {

@@ -718,8 +718,11 @@ def _arm_report(smp: PTSampler, chain: np.ndarray, wall: float, burn: int):
         with np.errstate(divide="ignore", invalid="ignore"):
             n_bm = float(np.nanmin(np.where(se > 0, var / se ** 2, np.inf)))
     st = smp.state
+    # integrated time of the ensemble mean implied by the batch-means ESS
+    tau_bm = float(post.shape[0] * post.shape[1] / n_bm) if n_bm > 0 else float("inf")
     return {
         "steps": int(len(chain)), "burn_in_steps": int(burn), "wall_s": round(wall, 2),
+        "ensemble_tau_batch_means": round(tau_bm, 2), "chain_over_50_ensemble_tau": bool(len(post) > 50 * tau_bm),
         "like_s": round(smp.like_seconds, 2), "tau": round(float(tau), 2), "ess": round(float(n_eff), 1),
         "ess_per_s": round(float(n_eff) / wall, 3), "chain_over_50_tau": bool(len(post) > 50 * tau),
         "ess_batch_means": round(n_bm, 1), "ess_batch_means_per_s": round(n_bm / wall, 3),
@@ -811,6 +814,10 @@ def ess_comparison(loglike: Callable, logprior: Callable, x0: np.ndarray, betas,
     # walker-averaged estimate misses correlation between walkers and
     # understates the error of an ensemble's mean
     out["accuracy"] = {"max_mean_diff_in_se": round(zmax, 3), "max_sd_rel_diff": round(sd_rel, 4),
+                       # the comparison needs runs longer than 50 times the
+                       # integrated time, here that of the ensemble mean
+                       "runs_over_50_ensemble_tau": bool(out["stretch"]["chain_over_50_ensemble_tau"] and
+                                                         out["stretch_flow"]["chain_over_50_ensemble_tau"]),
                        "max_mean_diff_in_batch_means_se": round(zmax_bm, 3),
                        "equal": bool(zmax_bm < 3 and sd_rel < 0.05),
                        "mean_diff_in_se": [round(float(v), 2) for v in z],

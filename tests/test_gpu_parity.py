@@ -122,6 +122,31 @@ def test_determinism_and_batch_composition(small):
     torch.cuda.synchronize()
 
 
+def test_graph_follows_the_callers_buffers(small):
+    """The captured graph reads the caller's parameter buffer and writes the
+    caller's ln L buffer directly: launches back to back on one stream with
+    alternating buffers (no synchronisation between them) give each buffer
+    its own walkers' values, bitwise those of separate synchronised calls."""
+    import torch
+    w, psd, d, L = small
+    print("case: graph launches on alternating caller buffers", flush=True)
+    B = 6
+    sets = [w.walkers[:B], w.walkers[2:2 + B], w.walkers[::-1][:B].copy()]
+    ref = [L.loglike(x).cpu().numpy() for x in sets]
+    p = [torch.as_tensor(x, dtype=torch.float64, device="cuda") for x in sets]
+    o = [torch.full((B,), float("nan"), dtype=torch.float64, device="cuda") for _ in sets]
+    for rep in range(3):
+        for i in (0, 1, 2, 1, 0):
+            L.loglike(p[i], out=o[i])
+    torch.cuda.synchronize()
+    for i in range(3):
+        assert np.array_equal(o[i].cpu().numpy(), ref[i])
+    # the same buffer with new contents is read afresh
+    p[0].copy_(p[1])
+    L.loglike(p[0], out=o[0])
+    assert np.array_equal(o[0].cpu().numpy(), ref[1])
+
+
 def test_schedules_give_identical_bits(small):
     """Every launch shape of the dense kernel (blocks per CU, one workgroup
     per walker) and the autotuner's choice give bitwise the same ln L."""
