@@ -220,7 +220,10 @@ typedef struct mbh_flow mbh_flow;
  * every layer; NULL draws the permutations from 'seed'.  Initial weights are
  * drawn from 'seed' (uniform, scale 1/sqrt(fan-in)) except W3 and b3, which
  * start at zero so that the initial flow is the identity map.  Synchronous;
- * on failure *out is NULL and nothing is leaked. */
+ * on failure *out is NULL and nothing is leaked.  EINVAL also if one
+ * layer's small weights (W1, b1, b2, W3, b3) and two hidden activations of
+ * 16 rows do not fit the current device's LDS per workgroup (about 87 KB at
+ * dim = 32, H = 256; under 64 KB for every dim up to H = 160). */
 mbh_status mbh_flow_create(int dim, int n_layers, int hidden, int max_batch, const int *perm_host, uint64_t seed,
                            mbh_flow **out);
 void mbh_flow_destroy(mbh_flow *flow);

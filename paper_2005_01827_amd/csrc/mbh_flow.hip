@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -73,6 +74,22 @@ __device__ __forceinline__ LayerW layer_w(const FlowArgs &a, int l)
     return w;
 }
 
+// The backward kernel reads rows of W1, W2 and W3 kU at a time into
+// registers, the next batch issued before the current one is used, so that a
+// thread has up to 2 kU loads in flight instead of one dependent load per
+// multiply-add.  The order of the multiply-adds is unchanged.
+constexpr int kU = 16;
+static_assert(kMaxO <= 2 * kU, "a row of the output map must fit two weight batches");
+
+// w[q] = row[j0 + q]; entries at or past jmax (>= 1) load entry jmax - 1
+// instead, so a batch is kU loads with no branch or select that would wait
+// for them (the caller skips those entries).
+__device__ __forceinline__ void load_run(float (&w)[kU], const float *__restrict__ row, int j0, int jmax)
+{
+#pragma unroll
+    for (int q = 0; q < kU; ++q) w[q] = row[min(j0 + q, jmax - 1)];
+}
+
 // acc[s] += w * v[s] for the 16 rows of one LDS column v (16-byte aligned).
 __device__ __forceinline__ void fma16(float (&acc)[kS], float w, const float *v)
 {
@@ -87,30 +104,101 @@ __device__ __forceinline__ void fma16(float (&acc)[kS], float w, const float *v)
     }
 }
 
+// Weights of one layer staged in LDS by the pass kernel: W1 [nc][H] and b1,
+// then b2, W3 [H][no] and b3 (two contiguous runs of the parameter array).
+// W2 [H][H] stays in global memory and is read column by column in batches.
+__host__ __device__ inline int stage_floats(int nc, int H, int no) { return nc * H + 2 * H + H * no + no; }
+constexpr int kPassThreads = 256;
+constexpr size_t kPassStaticLds = 8192;   // bound on the pass kernel's static LDS
+constexpr int kStageBatch = 16;           // staged floats per thread per round of loads
+// The second hidden layer, h2 = tanh(h1 W2 + b2) for the workgroup's 16 rows,
+// is a [16 x H] x [H x H] product: it runs on the matrix cores as 16 x 16
+// output tiles (v_mfma_f32_16x16x4f32, FP32 in and out), K in items of
+// kKSteps steps of 4.  Lane l of a wavefront supplies A[i][k] = h1 of row
+// l % 16, unit k0 + l / 16, and B[k][j] = W2[k0 + l / 16][j0 + l % 16], and
+// receives D[4 (l / 16) + v][j0 + l % 16], v = 0..3.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kKSteps = 32;
+constexpr int kKItem = 4 * kKSteps;   // rows of W2 per item
+constexpr int kWaves = kPassThreads / 64;
+__host__ __device__ inline int h_padded(int H) { return (H + kKItem - 1) / kKItem * kKItem; }
+
+// B operand of item (tile t, K block kb): rows and columns past H repeat
+// row / column H - 1; the rows meet zero padding of h1, the columns are
+// never written.
+__device__ __forceinline__ void load_w2_item(float (&b)[kKSteps], const float *__restrict__ W2, int H, int t,
+                                             int kb, int ln)
+{
+    const int col = min(t * 16 + (ln & 15), H - 1);
+    const int r0 = kb * kKItem + (ln >> 4);
+#pragma unroll
+    for (int q = 0; q < kKSteps; ++q) b[q] = W2[(size_t)min(r0 + 4 * q, H - 1) * H + col];
+}
+
+// acc += h1[rows][kb block] x W2[kb block][tile] (h1t is [unit][row], zero past H)
+__device__ __forceinline__ void mfma_item(f32x4 &acc, const float (&b)[kKSteps], const float *h1t, int kb, int ln)
+{
+    const float *a = h1t + (size_t)(kb * kKItem + (ln >> 4)) * kS + (ln & 15);
+#pragma unroll
+    for (int q = 0; q < kKSteps; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[4 * q * kS], b[q], acc, 0, 0, 0);
+}
+
 // One pass through all layers for kS rows: forward (u -> z) or inverse
 // (z -> u).  With kStore (forward only) the per-layer inputs X[l], hidden
 // activations H1[l], H2[l] and scales SV[l] are written for the backward
 // pass, X[L] = z, and logq goes to 'logq'.
-template <bool kInv, bool kStore>
-__global__ __launch_bounds__(256) void k_flow_pass(FlowArgs a, const float *__restrict__ in, float *__restrict__ out,
-                                                   float *__restrict__ logq, float *__restrict__ X,
-                                                   float *__restrict__ H1, float *__restrict__ H2,
-                                                   float *__restrict__ SV)
+//
+// A pass over a few hundred rows runs a handful of workgroups, so its time
+// is the chain of dependent steps through the layers, and every global read
+// waits for memory beyond L2 (the L2 does not keep the weights from one
+// launch to the next).  Hence, per layer: one burst of loads stages the
+// small weights (W1, W3, biases, the permutation) in LDS and loads each
+// wavefront's first two W2 items into registers.  For the first hidden
+// layer the kS rows are split between kS / kR groups of H threads, thread
+// (group g, unit j) computing unit j for rows g kR .. g kR + kR - 1 (the
+// results do not depend on kR).  The second hidden layer runs on the matrix
+// cores (above), the four wavefronts taking every fourth output tile, with
+// the next W2 item in flight while one is multiplied.
+template <bool kInv, bool kStore, int kR>
+__global__ __launch_bounds__(kPassThreads) void k_flow_pass(FlowArgs a, const float *__restrict__ in,
+                                                            float *__restrict__ out, float *__restrict__ logq,
+                                                            float *__restrict__ X, float *__restrict__ H1,
+                                                            float *__restrict__ H2, float *__restrict__ SV)
 {
+    static_assert(kS % kR == 0 && kR % 4 == 0, "row groups of whole float4 columns");
+    constexpr int kG = kS / kR;
     __shared__ float xs[kS][kMaxDim];
-    __shared__ __align__(16) float h1t[kMaxH * kS];
-    __shared__ __align__(16) float h2t[kMaxH * kS];
     __shared__ float ob[kS][kMaxO];
     __shared__ float ld[kS];
     __shared__ float sq[kS];
-
-    const int tid = threadIdx.x, nth = blockDim.x;
+    __shared__ int lnc[kMaxLayers];
+    __shared__ long long loff[kMaxLayers];
+    __shared__ int lperm[kMaxDim];
+    extern __shared__ float4 dyn4[];
+    const int tid = threadIdx.x;
     const int row0 = blockIdx.x * kS;
-    const int dim = a.dim, H = a.H, n = a.n;
-    for (int e = tid; e < kS * dim; e += nth) {
+    const int dim = a.dim, H = a.H, n = a.n, Hp = h_padded(H);
+    float *h1t = reinterpret_cast<float *>(dyn4);   // [Hp][kS], rows H.. Hp-1 zero
+    float *h2t = h1t + Hp * kS;                      // [H][kS]
+    float *wsm = h2t + H * kS;                       // staged weights of the current layer
+    // thread -> (row group, hidden unit); threads beyond kG H only help with the staging
+    const int grp = tid / H, j = tid - grp * H;
+    const bool unit = grp < kG;
+    const int rg = grp * kR;
+    // wavefront -> output tiles wv, wv + kWaves, ... of the second hidden layer
+    const int wv = tid >> 6, ln = tid & 63;
+    const int ntile = (H + 15) / 16, nkb = h_padded(H) / kKItem;
+    const int nit = (wv < ntile ? (ntile - wv + kWaves - 1) / kWaves : 0) * nkb;
+
+    for (int e = tid; e < kS * dim; e += kPassThreads) {
         const int s = e / dim, c = e - s * dim, r = row0 + s;
         xs[s][c] = r < n ? in[(size_t)r * dim + c] : 0.f;
     }
+    if (tid < a.L) {
+        lnc[tid] = a.nc[tid];
+        loff[tid] = a.off[tid];
+    }
+    for (int e = H * kS + tid; e < Hp * kS; e += kPassThreads) h1t[e] = 0.f;
     if (tid < kS) ld[tid] = 0.f;
     __syncthreads();
     if (kInv && tid < kS) {
@@ -121,77 +209,123 @@ __global__ __launch_bounds__(256) void k_flow_pass(FlowArgs a, const float *__re
 
     for (int li = 0; li < a.L; ++li) {
         const int l = kInv ? a.L - 1 - li : li;
-        const LayerW w = layer_w(a, l);
+        const int nc = lnc[l], nt = dim - nc, no = 2 * nt;
+        const float *gw = a.params + loff[l];
+        const float *W2 = gw + nc * H + H;
+        const int len1 = nc * H + H, len2 = H + H * no + no, tot = len1 + len2;
+        // burst: the permutation, the first two W2 items and the staged weights
+        const int pv = tid < dim ? a.perm[l * dim + tid] : 0;
+        float bA[kKSteps], bB[kKSteps];
+        if (nit > 0) load_w2_item(bA, W2, H, wv, 0, ln);
+        if (nit > 1) load_w2_item(bB, W2, H, wv + kWaves * (1 / nkb), 1 % nkb, ln);
+        for (int e0 = tid; e0 < tot; e0 += kStageBatch * kPassThreads) {
+            float v[kStageBatch];
+#pragma unroll
+            for (int q = 0; q < kStageBatch; ++q) {
+                const int e = min(e0 + q * kPassThreads, tot - 1);
+                v[q] = *(e < len1 ? gw + e : W2 + (size_t)H * H + (e - len1));
+            }
+#pragma unroll
+            for (int q = 0; q < kStageBatch; ++q) {
+                const int e = e0 + q * kPassThreads;
+                if (e < tot) wsm[e] = v[q];
+            }
+        }
+        if (tid < dim) lperm[tid] = pv;
         if (kStore) {
-            for (int e = tid; e < kS * dim; e += nth) {
+            for (int e = tid; e < kS * dim; e += kPassThreads) {
                 const int s = e / dim, c = e - s * dim, r = row0 + s;
                 if (r < n) X[((size_t)l * n + r) * dim + c] = xs[s][c];
             }
         }
+        __syncthreads();
+        const float *W1s = wsm, *b1s = wsm + nc * H, *b2s = wsm + len1, *W3s = b2s + H, *b3s = W3s + H * no;
         // h1 = tanh(x_c W1 + b1)
-        for (int j = tid; j < H; j += nth) {
-            float acc[kS];
-            const float bj = w.b1[j];
+        if (unit) {
+            float acc[kR];
+            const float bj = b1s[j];
 #pragma unroll
-            for (int s = 0; s < kS; ++s) acc[s] = bj;
-            for (int i = 0; i < w.nc; ++i) {
-                const float wij = w.W1[i * H + j];
-                const int c = w.p[i];
+            for (int r = 0; r < kR; ++r) acc[r] = bj;
+            for (int i = 0; i < nc; ++i) {
+                const float wij = W1s[i * H + j];
+                const int c = lperm[i];
 #pragma unroll
-                for (int s = 0; s < kS; ++s) acc[s] = fmaf(wij, xs[s][c], acc[s]);
+                for (int r = 0; r < kR; ++r) acc[r] = fmaf(wij, xs[rg + r][c], acc[r]);
             }
 #pragma unroll
-            for (int s = 0; s < kS; ++s) {
-                const float h = tanhf(acc[s]);
-                h1t[j * kS + s] = h;
-                if (kStore && row0 + s < n) H1[((size_t)l * n + row0 + s) * H + j] = h;
+            for (int r = 0; r < kR; ++r) {
+                const float h = tanhf(acc[r]);
+                h1t[j * kS + rg + r] = h;
+                if (kStore && row0 + rg + r < n) H1[((size_t)l * n + row0 + rg + r) * H + j] = h;
             }
         }
         __syncthreads();
-        // h2 = tanh(h1 W2 + b2)
-        for (int j = tid; j < H; j += nth) {
-            float acc[kS];
-            const float bj = w.b2[j];
+        // h2 = tanh(h1 W2 + b2): items (tile wv + kWaves m, K block kb) in order
+        {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            auto item = [&](int it, const float(&b)[kKSteps]) {
+                const int t = wv + kWaves * (it / nkb), kb = it % nkb;
+                const int col = t * 16 + (ln & 15);
+                if (kb == 0) {
+                    const float bj = b2s[min(col, H - 1)];
+                    acc = f32x4{bj, bj, bj, bj};
+                }
+                mfma_item(acc, b, h1t, kb, ln);
+                if (kb == nkb - 1 && col < H) {
+                    const int r4 = 4 * (ln >> 4);
+                    float4 h;
+                    h.x = tanhf(acc[0]);
+                    h.y = tanhf(acc[1]);
+                    h.z = tanhf(acc[2]);
+                    h.w = tanhf(acc[3]);
+                    *reinterpret_cast<float4 *>(&h2t[col * kS + r4]) = h;
+                    if (kStore) {
+                        const float hv[4] = {h.x, h.y, h.z, h.w};
 #pragma unroll
-            for (int s = 0; s < kS; ++s) acc[s] = bj;
-            for (int i = 0; i < H; ++i) fma16(acc, w.W2[i * H + j], &h1t[i * kS]);
-#pragma unroll
-            for (int s = 0; s < kS; ++s) {
-                const float h = tanhf(acc[s]);
-                h2t[j * kS + s] = h;
-                if (kStore && row0 + s < n) H2[((size_t)l * n + row0 + s) * H + j] = h;
+                        for (int v = 0; v < 4; ++v)
+                            if (row0 + r4 + v < n) H2[((size_t)l * n + row0 + r4 + v) * H + col] = hv[v];
+                    }
+                }
+            };
+            for (int it = 0; it < nit; it += 2) {
+                item(it, bA);
+                if (it + 2 < nit) load_w2_item(bA, W2, H, wv + kWaves * ((it + 2) / nkb), (it + 2) % nkb, ln);
+                if (it + 1 < nit) {
+                    item(it + 1, bB);
+                    if (it + 3 < nit) load_w2_item(bB, W2, H, wv + kWaves * ((it + 3) / nkb), (it + 3) % nkb, ln);
+                }
             }
         }
         __syncthreads();
         // o = h2 W3 + b3
-        for (int e = tid; e < kS * w.no; e += nth) {
-            const int s = e / w.no, k = e - s * w.no;
-            float acc = w.b3[k];
-            for (int i = 0; i < H; ++i) acc = fmaf(h2t[i * kS + s], w.W3[i * w.no + k], acc);
+        for (int e = tid; e < kS * no; e += kPassThreads) {
+            const int s = e / no, k = e - s * no;
+            float acc = b3s[k];
+            for (int i = 0; i < H; ++i) acc = fmaf(h2t[i * kS + s], W3s[i * no + k], acc);
             ob[s][k] = acc;
         }
         __syncthreads();
         // y_t = x_t exp(s) + t  (inverse: x_t = (y_t - t) exp(-s)); ob[s][j] <- s
-        for (int e = tid; e < kS * w.nt; e += nth) {
-            const int s = e / w.nt, j = e - s * w.nt;
-            const float sv = tanhf(ob[s][j]);
-            const float t = ob[s][w.nt + j];
-            const int c = w.p[w.nc + j];
+        for (int e = tid; e < kS * nt; e += kPassThreads) {
+            const int s = e / nt, jj = e - s * nt;
+            const float sv = tanhf(ob[s][jj]);
+            const float t = ob[s][nt + jj];
+            const int c = lperm[nc + jj];
             const float x = xs[s][c];
             xs[s][c] = kInv ? (x - t) * expf(-sv) : fmaf(x, expf(sv), t);
-            ob[s][j] = sv;
-            if (kStore && row0 + s < n) SV[((size_t)l * n + row0 + s) * a.ntmax + j] = sv;
+            ob[s][jj] = sv;
+            if (kStore && row0 + s < n) SV[((size_t)l * n + row0 + s) * a.ntmax + jj] = sv;
         }
         __syncthreads();
         if (tid < kS) {
             float acc = ld[tid];
-            for (int j = 0; j < w.nt; ++j) acc += ob[tid][j];
+            for (int jj = 0; jj < nt; ++jj) acc += ob[tid][jj];
             ld[tid] = acc;
         }
         __syncthreads();
     }
 
-    for (int e = tid; e < kS * dim; e += nth) {
+    for (int e = tid; e < kS * dim; e += kPassThreads) {
         const int s = e / dim, c = e - s * dim, r = row0 + s;
         if (r < n) {
             if (out) out[(size_t)r * dim + c] = xs[s][c];
@@ -208,6 +342,20 @@ __global__ __launch_bounds__(256) void k_flow_pass(FlowArgs a, const float *__re
         }
         logq[row0 + tid] = -0.5f * q - dim * kHalfLog2Pi + ld[tid];
     }
+}
+
+// Launch of the pass kernel for H hidden units: row groups of 8 when two
+// groups of H threads fit the workgroup, else one group of 16.
+template <bool kInv, bool kStore>
+hipError_t launch_pass(const FlowArgs &a, int H, size_t lds, const float *in, float *out, float *logq, float *X,
+                       float *H1, float *H2, float *SV, hipStream_t st)
+{
+    const unsigned blocks = (unsigned)((a.n + kS - 1) / kS);
+    if (2 * H <= kPassThreads)
+        k_flow_pass<kInv, kStore, kS / 2><<<blocks, kPassThreads, lds, st>>>(a, in, out, logq, X, H1, H2, SV);
+    else
+        k_flow_pass<kInv, kStore, kS><<<blocks, kPassThreads, lds, st>>>(a, in, out, logq, X, H1, H2, SV);
+    return hipGetLastError();
 }
 
 // Per-row backward pass of loss = -(1/n) sum log q: writes the gradients of
@@ -275,10 +423,18 @@ __global__ __launch_bounds__(256) void k_flow_back(FlowArgs a, const float *__re
         // d loss / d pre2 = (W3 go) * (1 - h2^2), in place over h2
         for (int j = tid; j < H; j += nth) {
             const float *w3 = w.W3 + j * w.no;
+            float wa[kU], wb[kU];
+            load_run(wa, w3, 0, w.no);
+            load_run(wb, w3, kU, w.no);
 #pragma unroll
             for (int s = 0; s < kS; ++s) {
                 float acc = 0.f;
-                for (int k = 0; k < w.no; ++k) acc = fmaf(w3[k], gob[s][k], acc);
+#pragma unroll
+                for (int k = 0; k < kU; ++k)
+                    if (k < w.no) acc = fmaf(wa[k], gob[s][k], acc);
+#pragma unroll
+                for (int k = 0; k < kU; ++k)
+                    if (kU + k < w.no) acc = fmaf(wb[k], gob[s][kU + k], acc);
                 const float h = h2t[j * kS + s];
                 const float g = acc * (1.f - h * h);
                 h2t[j * kS + s] = g;
@@ -292,7 +448,18 @@ __global__ __launch_bounds__(256) void k_flow_back(FlowArgs a, const float *__re
 #pragma unroll
             for (int s = 0; s < kS; ++s) acc[s] = 0.f;
             const float *w2 = w.W2 + (size_t)i * H;
-            for (int j = 0; j < H; ++j) fma16(acc, w2[j], &h2t[j * kS]);
+            float wa[kU], wb[kU];
+            load_run(wa, w2, 0, H);
+            for (int j0 = 0; j0 < H; j0 += 2 * kU) {
+                load_run(wb, w2, j0 + kU, H);
+#pragma unroll
+                for (int q = 0; q < kU; ++q)
+                    if (j0 + q < H) fma16(acc, wa[q], &h2t[(j0 + q) * kS]);
+                load_run(wa, w2, j0 + 2 * kU, H);
+#pragma unroll
+                for (int q = 0; q < kU; ++q)
+                    if (j0 + kU + q < H) fma16(acc, wb[q], &h2t[(j0 + kU + q) * kS]);
+            }
 #pragma unroll
             for (int s = 0; s < kS; ++s) {
                 const float h = h1t[i * kS + s];
@@ -307,7 +474,18 @@ __global__ __launch_bounds__(256) void k_flow_back(FlowArgs a, const float *__re
             const int s = e / w.nc, i = e - s * w.nc;
             const float *w1 = w.W1 + (size_t)i * H;
             float acc = 0.f;
-            for (int j = 0; j < H; ++j) acc = fmaf(w1[j], h1t[j * kS + s], acc);
+            float wa[kU], wb[kU];
+            load_run(wa, w1, 0, H);
+            for (int j0 = 0; j0 < H; j0 += 2 * kU) {
+                load_run(wb, w1, j0 + kU, H);
+#pragma unroll
+                for (int q = 0; q < kU; ++q)
+                    if (j0 + q < H) acc = fmaf(wa[q], h1t[(j0 + q) * kS + s], acc);
+                load_run(wa, w1, j0 + 2 * kU, H);
+#pragma unroll
+                for (int q = 0; q < kU; ++q)
+                    if (j0 + kU + q < H) acc = fmaf(wb[q], h1t[(j0 + kU + q) * kS + s], acc);
+            }
             gx[s][w.p[i]] += acc;
         }
         __syncthreads();
@@ -411,6 +589,7 @@ double uniform01(uint64_t &s) { return (splitmix64(s) >> 11) * (1.0 / 9007199254
 struct mbh_flow {
     int dim = 0, L = 0, H = 0, max_batch = 0, ntmax = 0;
     long long P = 0;
+    size_t pass_lds = 0;   // dynamic LDS bytes of the pass kernel
     std::vector<int> perm, nc;
     std::vector<long long> off;
     int *d_perm = nullptr, *d_nc = nullptr;
@@ -546,6 +725,19 @@ mbh_status mbh_flow_create(int dim, int n_layers, int hidden, int max_batch, con
     }
     f->off[n_layers] = P;
     f->P = P;
+    int stage = 0;
+    for (int l = 0; l < n_layers; ++l) stage = std::max(stage, stage_floats(f->nc[l], hidden, 2 * (dim - f->nc[l])));
+    f->pass_lds = sizeof(float) * ((size_t)(h_padded(hidden) + hidden) * kS + (size_t)stage);
+    {
+        int dev = 0, lds_max = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+            f->pass_lds + kPassStaticLds > (size_t)lds_max) {
+            (void)hipGetLastError();
+            delete f;
+            return MBH_EINVAL;
+        }
+    }
 
     // Initial weights: U(-1/sqrt(fan_in), 1/sqrt(fan_in)); the output map is zero.
     std::vector<float> p0((size_t)P, 0.f);
@@ -638,9 +830,8 @@ mbh_status mbh_flow_forward(mbh_flow *f, const float *u_dev, int n, float *z_dev
     if (mbh_status s = check_rows(f, u_dev, z_dev, n)) return s;
     if (n == 0) return MBH_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    k_flow_pass<false, false><<<(n + kS - 1) / kS, pass_threads(f->H), 0, st>>>(args(f, n), u_dev, z_dev, logq_dev,
-                                                                             nullptr, nullptr, nullptr, nullptr);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_pass<false, false>(args(f, n), f->H, f->pass_lds, u_dev, z_dev, logq_dev, nullptr, nullptr,
+                                             nullptr, nullptr, st);
     return e == hipSuccess ? MBH_OK : fhip(f, e, "k_flow_pass launch");
 }
 
@@ -650,9 +841,8 @@ mbh_status mbh_flow_inverse(mbh_flow *f, const float *z_dev, int n, float *u_dev
     if (mbh_status s = check_rows(f, z_dev, u_dev, n)) return s;
     if (n == 0) return MBH_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    k_flow_pass<true, false><<<(n + kS - 1) / kS, pass_threads(f->H), 0, st>>>(args(f, n), z_dev, u_dev, logq_dev,
-                                                                            nullptr, nullptr, nullptr, nullptr);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_pass<true, false>(args(f, n), f->H, f->pass_lds, z_dev, u_dev, logq_dev, nullptr, nullptr,
+                                            nullptr, nullptr, st);
     return e == hipSuccess ? MBH_OK : fhip(f, e, "k_flow_pass launch");
 }
 
@@ -666,7 +856,9 @@ mbh_status mbh_flow_loss_grad(mbh_flow *f, const float *u_dev, int n, double *lo
     hipStream_t st = static_cast<hipStream_t>(stream);
     const FlowArgs a = args(f, n);
     const int blocks = (n + kS - 1) / kS, th = pass_threads(f->H);
-    k_flow_pass<false, true><<<blocks, th, 0, st>>>(a, u_dev, nullptr, f->logq, f->X, f->H1, f->H2, f->SV);
+    hipError_t e = launch_pass<false, true>(a, f->H, f->pass_lds, u_dev, nullptr, f->logq, f->X, f->H1, f->H2, f->SV,
+                                            st);
+    if (e != hipSuccess) return fhip(f, e, "k_flow_pass launch");
     k_flow_back<<<blocks, th, 0, st>>>(a, f->X, f->H1, f->H2, f->SV, f->Go, f->Gp1, f->Gp2, 1.0f / n);
     int chunk = (n + kMaxChunks - 1) / kMaxChunks;
     if (chunk < kMinChunk) chunk = kMinChunk;
@@ -676,7 +868,7 @@ mbh_status mbh_flow_loss_grad(mbh_flow *f, const float *u_dev, int n, double *lo
                                                    f->partial);
     k_flow_gsum<<<gq, 256, 0, st>>>(f->partial, nchunk, f->P, f->grad);
     k_flow_loss<<<1, 256, 0, st>>>(f->logq, n, f->loss);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return fhip(f, e, "flow training launch");
     if (loss_host) e = hipMemcpyAsync(loss_host, f->loss, sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && grad_host)

@@ -157,14 +157,25 @@ __device__ __forceinline__ int first_bin(double x, double df)
 constexpr int kSplineThreads = 256;
 constexpr int kSplineRows = 4;     // rows per thread: ns - 2 <= 1024
 
-// Functions solved together: all eight while their right-hand sides fit in
-// LDS beside the matrix, else four at a time.
-__host__ __device__ inline int spline_group(int ns) { return ns <= 512 ? kNumFn : kNumFn / 2; }
-inline size_t spline_lds_bytes(int ns)
+// LDS of one spline workgroup solving G functions together: the matrix
+// (3 m) and the reciprocals of its diagonal (m), G right-hand sides, 2 G end
+// values, the knots, the reciprocal interval widths and the knots' first
+// dense bins.
+constexpr size_t kSplineLdsMax = 65536;
+__host__ __device__ inline size_t spline_lds_for(int ns, int G)
 {
-    const int m = ns - 2, G = spline_group(ns);
-    return sizeof(double) * ((size_t)(3 + G) * m + 2 * G);
+    const size_t m = (size_t)ns - 2;
+    return sizeof(double) * ((4 + G) * m + 2 * G + ns + (ns - 1)) + sizeof(int) * ns;
 }
+// Functions solved together: the most of 8, 4, 2, 1 that fit in LDS (all
+// eight up to 512 knots, one at 1024).
+__host__ __device__ inline int spline_group(int ns)
+{
+    int G = kNumFn;
+    while (G > 1 && spline_lds_for(ns, G) > kSplineLdsMax) G /= 2;
+    return G;
+}
+inline size_t spline_lds_bytes(int ns) { return spline_lds_for(ns, spline_group(ns)); }
 
 // Not-a-knot splines through (f_j, y_j), one workgroup per (walker, mode).
 // Unknowns M_1..M_{ns-2} (second derivatives; row r <-> M_{r+1}); M_0 and
@@ -191,19 +202,31 @@ __global__ __launch_bounds__(kSplineThreads) void k_spline(int B, Modes md, Grid
     const int ns = g.ns, m = ns - 2;
     const int wm = blockIdx.x;
     if (wm >= B * md.nm) return;
-    const double *x = kf + (size_t)wm * ns;
+    const double *xg = kf + (size_t)wm * ns;
     double *out = coef + (size_t)wm * (ns - 1) * kCoefPerIv;
     const bool act = band[wm].active != 0;
+    double *A = sm, *Bm = sm + m, *C = sm + 2 * m, *D = sm + 3 * m;   // D[G][m]
+    double *M0 = D + (size_t)G * m, *M1 = M0 + G;                       // M_0, M_{ns-1} per function
+    double *x = M1 + G, *hinv = x + ns;                                 // knots, 1 / (x[i+1] - x[i])
+    double *binv = hinv + (ns - 1);                                     // 1 / b of every row, per round
+    int *kbl = reinterpret_cast<int *>(binv + m);                       // first dense bin of each knot
     {
         int *kb = kbin + (size_t)wm * ns;
-        for (int i = threadIdx.x; i < ns; i += kSplineThreads) kb[i] = act ? first_bin(x[i], g.df) : 0;
+        for (int i = threadIdx.x; i < ns; i += kSplineThreads) {
+            const double xi = xg[i];
+            const int k = act ? first_bin(xi, g.df) : 0;
+            kb[i] = k;
+            kbl[i] = k;
+            x[i] = xi;
+        }
     }
     if (!act) {
         for (int i = threadIdx.x; i < (ns - 1) * kCoefPerIv; i += kSplineThreads) out[i] = 0.0;
         return;
     }
-    double *A = sm, *Bm = sm + m, *C = sm + 2 * m, *D = sm + 3 * m;   // D[G][m]
-    double *M0 = D + (size_t)G * m, *M1 = M0 + G;                       // M_0, M_{ns-1} per function
+    __syncthreads();
+    for (int i = threadIdx.x; i < ns - 1; i += kSplineThreads) hinv[i] = 1.0 / (x[i + 1] - x[i]);
+    __syncthreads();
     for (int q0 = 0; q0 < kNumFn; q0 += G) {
         // the system: matrix rows and right-hand sides 6 (s_{i} - s_{i-1})
         for (int r = threadIdx.x; r < m; r += kSplineThreads) {
@@ -225,20 +248,23 @@ __global__ __launch_bounds__(kSplineThreads) void k_spline(int B, Modes md, Grid
             C[r] = sup;
             for (int q = 0; q < G; ++q) {
                 const double *y = fn + ((size_t)wm * kNumFn + q0 + q) * ns;
-                D[(size_t)q * m + r] = 6.0 * ((y[i + 1] - y[i]) / h1 - (y[i] - y[i - 1]) / h0);
+                D[(size_t)q * m + r] = 6.0 * ((y[i + 1] - y[i]) * hinv[i] - (y[i] - y[i - 1]) * hinv[i - 1]);
             }
         }
         __syncthreads();
-        // cyclic reduction rounds
+        // cyclic reduction rounds; each round first forms 1 / b of every
+        // row, one division per row instead of one per neighbour
         for (int s = 1; s < m; s *= 2) {
+            for (int r = threadIdx.x; r < m; r += kSplineThreads) binv[r] = 1.0 / Bm[r];
+            __syncthreads();
             double na[kSplineRows], nb[kSplineRows], nc[kSplineRows], nd[kSplineRows][G];
 #pragma unroll
             for (int u = 0; u < kSplineRows; ++u) {
                 const int r = threadIdx.x + u * kSplineThreads;
                 if (r >= m) continue;
                 const bool lo = r - s >= 0, hi = r + s < m;
-                const double al = lo ? -A[r] / Bm[r - s] : 0.0;
-                const double ga = hi ? -C[r] / Bm[r + s] : 0.0;
+                const double al = lo ? -A[r] * binv[r - s] : 0.0;
+                const double ga = hi ? -C[r] * binv[r + s] : 0.0;
                 na[u] = lo ? al * A[r - s] : 0.0;
                 nc[u] = hi ? ga * C[r + s] : 0.0;
                 nb[u] = Bm[r] + (lo ? al * C[r - s] : 0.0) + (hi ? ga * A[r + s] : 0.0);
@@ -280,10 +306,10 @@ __global__ __launch_bounds__(kSplineThreads) void k_spline(int B, Modes md, Grid
             const double *y = fn + ((size_t)wm * kNumFn + q0 + q) * ns;
             const double mi = i == 0 ? M0[q] : Mq[i - 1];
             const double mj = i + 1 == ns - 1 ? M1[q] : Mq[i];
-            const double x0 = x[i], h = x[i + 1] - x0;
-            const double sl = (y[i + 1] - y[i]) / h;
-            const double p0 = y[i], p1 = sl - h * (2.0 * mi + mj) / 6.0, p2 = 0.5 * mi, p3 = (mj - mi) / (6.0 * h);
-            const double dl = (double)first_bin(x[i + 1], g.df) * g.df - x0;
+            const double x0 = x[i], h = x[i + 1] - x0, hi = hinv[i];
+            const double sl = (y[i + 1] - y[i]) * hi;
+            const double p0 = y[i], p1 = sl - h * (2.0 * mi + mj) / 6.0, p2 = 0.5 * mi, p3 = (mj - mi) * hi / 6.0;
+            const double dl = (double)kbl[i + 1] * g.df - x0;
             double *o = out + (size_t)i * kCoefPerIv + (q0 + q) * 4;
             o[0] = fma(fma(fma(p3, dl, p2), dl, p1), dl, p0);
             o[1] = fma(fma(3.0 * p3, dl, 2.0 * p2), dl, p1);
@@ -307,12 +333,22 @@ hipError_t launch_response(int B, const Modes &md, const GridDesc &g, const Work
 hipError_t launch_spline(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st)
 {
     if (B <= 0) return hipSuccess;
-    if (spline_group(g.ns) == kNumFn)
-        k_spline<kNumFn><<<B * md.nm, kSplineThreads, spline_lds_bytes(g.ns), st>>>(B, md, g, wk.band, wk.kf, wk.fn,
-                                                                                   wk.coef, wk.kbin);
-    else
-        k_spline<kNumFn / 2><<<B * md.nm, kSplineThreads, spline_lds_bytes(g.ns), st>>>(B, md, g, wk.band, wk.kf,
-                                                                                       wk.fn, wk.coef, wk.kbin);
+    const size_t lds = spline_lds_bytes(g.ns);
+    const unsigned grid = (unsigned)(B * md.nm);
+    switch (spline_group(g.ns)) {
+    case kNumFn:
+        k_spline<kNumFn><<<grid, kSplineThreads, lds, st>>>(B, md, g, wk.band, wk.kf, wk.fn, wk.coef, wk.kbin);
+        break;
+    case kNumFn / 2:
+        k_spline<kNumFn / 2><<<grid, kSplineThreads, lds, st>>>(B, md, g, wk.band, wk.kf, wk.fn, wk.coef, wk.kbin);
+        break;
+    case kNumFn / 4:
+        k_spline<kNumFn / 4><<<grid, kSplineThreads, lds, st>>>(B, md, g, wk.band, wk.kf, wk.fn, wk.coef, wk.kbin);
+        break;
+    default:
+        k_spline<1><<<grid, kSplineThreads, lds, st>>>(B, md, g, wk.band, wk.kf, wk.fn, wk.coef, wk.kbin);
+        break;
+    }
     return hipGetLastError();
 }
 

@@ -91,6 +91,35 @@ def test_inverse_matches_oracle_and_undoes_forward(mbh):
     fl.close()
 
 
+@pytest.mark.parametrize("dim,nl,hid", [(7, 3, 40), (32, 2, 16), (5, 1, 256)])
+def test_other_shapes_match_oracle(mbh, dim, nl, hid):
+    """Layer widths that are not a multiple of the kernels' 16-weight load
+    batches (40), the smallest (16) and largest (256) widths, the widest
+    input (32: 16 kept coordinates, 32 outputs per layer) and one layer:
+    forward, inverse and the gradient against the FP64 oracle."""
+    fl, perm, p = _setup(mbh, dim=dim, nl=nl, hid=hid, max_batch=4096)
+    p64 = p.astype(np.float64)
+    u = _rows(333, dim, 41 + dim)
+    z, lq = fl.forward(u)
+    z_ref, lq_ref = F.forward(p64, u.astype(np.float64), perm, hid)
+    z, lq = z.cpu().numpy().astype(np.float64), lq.cpu().numpy().astype(np.float64)
+    print(f"dim {dim} L {nl} H {hid}: max |dz| {np.abs(z - z_ref).max():.2e}, "
+          f"max |dlogq| {np.abs(lq - lq_ref).max():.2e}")
+    assert np.abs(z_ref - u).max() > 0.05
+    assert (np.abs(z - z_ref) / (2e-4 + 2e-5 * np.abs(z_ref))).max() < 1.0
+    assert np.abs(lq - lq_ref).max() < 1e-3
+    zz = _rows(77, dim, 43 + dim, scale=1.0)
+    uu, lqi = fl.inverse(zz)
+    u_ref, lqi_ref = F.inverse(p64, zz.astype(np.float64), perm, hid)
+    assert (np.abs(uu.cpu().numpy() - u_ref) / (2e-4 + 2e-5 * np.abs(u_ref))).max() < 1.0
+    assert np.abs(lqi.cpu().numpy() - lqi_ref).max() < 1e-3
+    loss, g = fl.loss_grad(u)
+    loss_ref, g_ref = F.loss_grad(p64, u.astype(np.float64), perm, hid)
+    assert abs(loss - loss_ref) < 1e-4 * max(1.0, abs(loss_ref))
+    assert np.abs(g.astype(np.float64) - g_ref).max() < 2e-4 * np.abs(g_ref).max()
+    fl.close()
+
+
 @pytest.mark.parametrize("n", [777, 20000])
 def test_loss_and_gradient_match_oracle(mbh, n):
     """777 rows: 3 full 256-row chunks and a ragged one; 20000 rows: 64
