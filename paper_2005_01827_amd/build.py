@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmbh.so")
-SOURCES = ["mbh_ctx.hip", "mbh_waveform.hip", "mbh_response.hip", "mbh_dense.hip", "mbh_flow.hip"]
+SOURCES = ["mbh_ctx.hip", "mbh_sparse.hip", "mbh_dense.hip", "mbh_flow.hip"]
 HEADERS = ["mbh_internal.h", os.path.join("..", "..", "include", "mbh.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

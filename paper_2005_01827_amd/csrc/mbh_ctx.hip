@@ -51,6 +51,7 @@ struct mbh_ctx {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         hipGraphNode_t src = nullptr, red = nullptr;
+        int src_nargs = 0;                // arguments of the kernel in node src (the parameters are argument 0)
         const double *params = nullptr;   // buffers the exec's nodes use now
         double *logL = nullptr;
     };
@@ -172,12 +173,21 @@ mbh_status enqueue_all(mbh_ctx *c, const double *params, int B, double *out7, do
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     hipError_t e;
-    if ((e = launch_waveform(params, B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "waveform");
-    if ((e = launch_response(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "response");
-    if ((e = launch_spline(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "spline");
+    // small batches: the sparse stage as one kernel (with one walker also
+    // the work-item list); larger ones: one kernel per step
+    const bool fused = B <= kFusedSparseMaxBatch;
+    if (fused) {
+        if ((e = launch_sparse(params, B, c->md, c->g, c->wk, c->max_items, true, st)) != hipSuccess)
+            return hip_fail(c, e, "sparse");
+    } else {
+        if ((e = launch_waveform(params, B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "waveform");
+        if ((e = launch_response(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "response");
+        if ((e = launch_spline(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "spline");
+    }
     if ((e = launch_coef32(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "coef32");
     if ((e = launch_walker_bands(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "bands");
-    if ((e = launch_dense(B, c->md, c->g, c->wk, data_of(c), c->max_items, c->sch, false, st, ev0, ev1)) != hipSuccess)
+    if ((e = launch_dense(B, c->md, c->g, c->wk, data_of(c), c->max_items, c->sch, false, st, ev0, ev1,
+                          fused && B == 1)) != hipSuccess)
         return hip_fail(c, e, "dense");
     if ((e = launch_reduce(B, c->g, c->wk, data_of(c), out7, logL, st)) != hipSuccess) return hip_fail(c, e, "reduce");
     return MBH_OK;
@@ -366,6 +376,7 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
     TRY(dalloc(c, &c->wk.item_t, (size_t)c->max_items));
     TRY(dalloc(c, &c->wk.tile_off, (size_t)ntile_max + 1));
     TRY(dalloc(c, &c->wk.ticket, (size_t)64));
+    TRY(dalloc(c, &c->wk.done, (size_t)1));
     TRY(dalloc(c, &c->wk.wbase, (size_t)B + 1));
     TRY(dalloc(c, &c->wk.partial, (size_t)c->max_items * kPartials));
     TRY(dalloc(c, &c->wk.out7, (size_t)B * 7));
@@ -389,6 +400,7 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
         (e = hipMemcpy(d_in, desc->data, sizeof(double) * 6 * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(c->wk.src, 0, sizeof(Source) * B)) != hipSuccess ||
         (e = hipMemset(c->wk.band, 0, sizeof(ModeBand) * B * nm)) != hipSuccess ||
+        (e = hipMemset(c->wk.done, 0, sizeof(int))) != hipSuccess ||
         (e = hipMemcpy(psd_dev, desc->psd, sizeof(double) * 3 * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = launch_setup_data(psd_dev, d_in, c->d, c->w, c->pre, scratch, c->dhi32, c->dlo32, c->sw32, c->g,
                                4.0 * desc->df, nullptr)) != hipSuccess ||
@@ -508,6 +520,11 @@ mbh_status mbh_loglike_batch(mbh_ctx *ctx, const double *params_dev, int B, doub
         mbh_ctx::GraphEntry ge;
         ge.graph = graph;
         ge.src = find_kernel_node(graph, source_kernel());
+        ge.src_nargs = 4;
+        if (!ge.src) {
+            ge.src = find_kernel_node(graph, sparse_kernel(ctx->g.ns));
+            ge.src_nargs = 5;
+        }
         ge.red = find_kernel_node(graph, reduce_kernel());
         ge.params = ctx->params;
         ge.logL = ctx->logL;
@@ -519,12 +536,14 @@ mbh_status mbh_loglike_batch(mbh_ctx *ctx, const double *params_dev, int B, doub
         it = ctx->graphs.emplace(B, ge).first;
     }
     mbh_ctx::GraphEntry &ge = it->second;
-    // the first kernel reads params (argument 0 of 4), the last writes ln L
-    // (argument 8 of 9); where a node was not found, the parameters and ln L
-    // go through the context's staging buffers instead
+    // the first kernel reads params (argument 0 of 4 in k_source, of 5 in
+    // k_sparse), the last writes ln L (argument 8 of 9); where a node was not
+    // found, the parameters and ln L go through the context's staging
+    // buffers instead
     const bool direct_in = ge.src != nullptr, direct_out = ge.red != nullptr;
     if (direct_in && ge.params != params_dev) {
-        if ((e = retarget(ge.exec, ge.src, 0, 4, params_dev)) != hipSuccess) return hip_fail(ctx, e, "graph node update");
+        if ((e = retarget(ge.exec, ge.src, 0, ge.src_nargs, params_dev)) != hipSuccess)
+            return hip_fail(ctx, e, "graph node update");
         ge.params = params_dev;
     }
     if (direct_out && ge.logL != logL_dev) {

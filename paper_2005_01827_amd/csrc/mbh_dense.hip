@@ -141,33 +141,6 @@ __global__ void k_scan_final(const double *__restrict__ e2, int n, const double 
 // ---------------------------------------------------------------------------
 // Work items.
 // ---------------------------------------------------------------------------
-// Union band of walker w's active modes and its range of tiles.
-__device__ WalkerBand walker_band(int w, int nm, const GridDesc &g, const Source *__restrict__ src,
-                                  const ModeBand *__restrict__ band)
-{
-    WalkerBand r;
-    r.klo = 0;
-    r.khi = -1;
-    r.tile_lo = 0;
-    r.ntiles = 0;
-    if (src[w].valid) {
-        int lo = 0x7fffffff, hi = -1;
-        for (int im = 0; im < nm; ++im) {
-            const ModeBand b = band[w * nm + im];
-            if (!b.active) continue;
-            lo = min(lo, b.klo);
-            hi = max(hi, b.khi);
-        }
-        if (hi >= lo) {
-            r.klo = lo;
-            r.khi = hi;
-            r.tile_lo = (lo - g.k0) / g.tile_bins;
-            r.ntiles = (hi - g.k0) / g.tile_bins - r.tile_lo + 1;
-        }
-    }
-    return r;
-}
-
 __global__ void k_walker_bands(int B, int nm, GridDesc g, const Source *__restrict__ src,
                                const ModeBand *__restrict__ band, WalkerBand *__restrict__ wb)
 {
@@ -176,31 +149,14 @@ __global__ void k_walker_bands(int B, int nm, GridDesc g, const Source *__restri
     wb[w] = walker_band(w, nm, g, src, band);
 }
 
-// A single walker: its band, the exclusive scan over walkers, the per-tile
-// offsets, the work items (its own tiles, in order) and the zeroed counter,
-// all in one workgroup.  These are the lists the general kernels build for
-// B = 1; one launch instead of five shortens the single-walker step.
+// A single walker's work-item list in one launch instead of five (items_one).
 __global__ __launch_bounds__(256) void k_items_one(int nm, GridDesc g, const Source *__restrict__ src,
                                                    const ModeBand *__restrict__ band, WalkerBand *__restrict__ wb,
                                                    int *__restrict__ wbase, int *__restrict__ tile_off,
                                                    int *__restrict__ ticket, int *__restrict__ item_w,
                                                    int *__restrict__ item_t, int max_items)
 {
-    __shared__ WalkerBand r;
-    if (threadIdx.x == 0) {
-        r = walker_band(0, nm, g, src, band);
-        wb[0] = r;
-        wbase[0] = 0;
-        wbase[1] = r.ntiles;
-        ticket[0] = 0;
-    }
-    __syncthreads();
-    const int ntiles = (g.n + g.tile_bins - 1) / g.tile_bins;
-    for (int t = threadIdx.x; t <= ntiles; t += blockDim.x) tile_off[t] = min(max(t - r.tile_lo, 0), r.ntiles);
-    for (int i = threadIdx.x; i < r.ntiles && i < max_items; i += blockDim.x) {
-        item_w[i] = 0;
-        item_t[i] = r.tile_lo + i;
-    }
+    items_one(nm, g, src, band, wb, wbase, tile_off, ticket, item_w, item_t, max_items);
 }
 
 // exclusive scan of ntiles over walkers (single block)
@@ -1223,10 +1179,11 @@ void launch_items(int B, int nm, const GridDesc &g, const Work &wk, int max_item
 }
 
 hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &wk, const Data &dt, int max_items,
-                        const Schedule &sch, bool inner, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1)
+                        const Schedule &sch, bool inner, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                        bool items_ready)
 {
     if (B <= 0) return hipSuccess;
-    launch_items(B, md.nm, g, wk, max_items, st);
+    if (!items_ready) launch_items(B, md.nm, g, wk, max_items, st);
     DenseArgs a = make_args(B, md, g, wk, dt, max_items);
     a.one_per_walker = sch.one_per_walker;
     a.use_ticket = sch.one_per_walker ? 0 : 1;

@@ -40,6 +40,7 @@ struct Source {
     double fJ, kRD, cR, b1, b0;             // merger-ringdown phase piece
     double fpeak, al0, al1;                 // alignment at max f^2 A_22
     double A0;                              // amplitude scale
+    double kv[3], ep[3], eq[3];             // propagation direction, polarization basis (lambda, beta, psi)
     int valid;
     int pad;
 };
@@ -107,7 +108,74 @@ struct Work {
     double *cis_tab;        // constants of the dense-stage sin/cos
     float *cis32;           // the same for the FP32 dense stage
     float *coef32;          // [B][nm][ns-1][32] FP32 copy of coef (FP32 dense stage)
+    int *done;              // mode workgroups of the single walker finished in k_sparse (0 between launches)
 };
+
+// Outputs of the fused sparse kernel (the Work arrays it writes) and, with
+// done set (one walker), the work-item list it builds.
+struct SparseArgs {
+    Source *src;
+    ModeBand *band;
+    double *kf, *kt, *fn, *coef;
+    int *kbin;
+    int *done;
+    WalkerBand *wband;
+    int *wbase, *tile_off, *ticket, *item_w, *item_t;
+    int max_items;
+};
+
+// Union band of walker w's active modes and its range of tiles.
+__device__ inline WalkerBand walker_band(int w, int nm, const GridDesc &g, const Source *__restrict__ src,
+                                         const ModeBand *__restrict__ band)
+{
+    WalkerBand r;
+    r.klo = 0;
+    r.khi = -1;
+    r.tile_lo = 0;
+    r.ntiles = 0;
+    if (src[w].valid) {
+        int lo = 0x7fffffff, hi = -1;
+        for (int im = 0; im < nm; ++im) {
+            const ModeBand b = band[w * nm + im];
+            if (!b.active) continue;
+            lo = min(lo, b.klo);
+            hi = max(hi, b.khi);
+        }
+        if (hi >= lo) {
+            r.klo = lo;
+            r.khi = hi;
+            r.tile_lo = (lo - g.k0) / g.tile_bins;
+            r.ntiles = (hi - g.k0) / g.tile_bins - r.tile_lo + 1;
+        }
+    }
+    return r;
+}
+
+// The work-item list of a single walker, built by one whole workgroup: its
+// band, the exclusive scan over walkers, the per-tile offsets, the items
+// (its own tiles, in order) and the zeroed counter, the lists the general
+// kernels build for B = 1.
+__device__ inline void items_one(int nm, const GridDesc &g, const Source *__restrict__ src,
+                                 const ModeBand *__restrict__ band, WalkerBand *__restrict__ wb,
+                                 int *__restrict__ wbase, int *__restrict__ tile_off, int *__restrict__ ticket,
+                                 int *__restrict__ item_w, int *__restrict__ item_t, int max_items)
+{
+    __shared__ WalkerBand r;
+    if (threadIdx.x == 0) {
+        r = walker_band(0, nm, g, src, band);
+        wb[0] = r;
+        wbase[0] = 0;
+        wbase[1] = r.ntiles;
+        ticket[0] = 0;
+    }
+    __syncthreads();
+    const int ntiles = (g.n + g.tile_bins - 1) / g.tile_bins;
+    for (int t = threadIdx.x; t <= ntiles; t += blockDim.x) tile_off[t] = min(max(t - r.tile_lo, 0), r.ntiles);
+    for (int i = threadIdx.x; i < r.ntiles && i < max_items; i += blockDim.x) {
+        item_w[i] = 0;
+        item_t[i] = r.tile_lo + i;
+    }
+}
 
 // Blocked layout of the data and weights read by the dense stage: bins in
 // blocks of 64, each block holding the 64 values of channel A, then E, then
@@ -155,6 +223,16 @@ hipError_t launch_response(int B, const Modes &md, const GridDesc &g, const Work
 
 hipError_t launch_spline(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st);
 
+// launch_waveform + launch_response + launch_spline as one kernel, one
+// workgroup per (walker, mode), writing the same bits; with items and
+// B = 1 it also builds the work-item list (launch_walker_bands is then not
+// needed).
+hipError_t launch_sparse(const double *params, int B, const Modes &md, const GridDesc &g, const Work &wk,
+                         int max_items, bool items, hipStream_t st);
+
+// Batches up to this size take the fused sparse kernel on the graph path.
+constexpr int kFusedSparseMaxBatch = 1;
+
 hipError_t launch_walker_bands(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st);
 
 // Launch shape of the dense kernel: blocks_per_cu workgroups per compute unit
@@ -171,9 +249,11 @@ int num_cus();
 // ev0/ev1 (optional) are recorded on st right before and after the dense
 // kernel.  inner = false: the FP64 path accumulates only the residual sums
 // (enough for ln L); <d|h>_c and <h|h>_c of the output are then zero.
+// items_ready: the work-item list is already built (launch_sparse with one
+// walker); otherwise the launch builds it first.
 hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &wk, const Data &dt,
                         int max_items, const Schedule &sch, bool inner, hipStream_t st, hipEvent_t ev0 = nullptr,
-                        hipEvent_t ev1 = nullptr);
+                        hipEvent_t ev1 = nullptr, bool items_ready = false);
 
 hipError_t launch_reduce(int B, const GridDesc &g, const Work &wk, const Data &dt, double *out7,
                          double *logL, hipStream_t st);
@@ -183,6 +263,7 @@ hipError_t launch_reduce(int B, const GridDesc &g, const Work &wk, const Data &d
 // context finds their nodes in a captured graph and points them at the
 // caller's buffers for each launch.
 const void *source_kernel();
+const void *sparse_kernel(int ns);   // the fused sparse kernel launch_sparse uses for ns knots
 const void *reduce_kernel();
 
 hipError_t launch_template(const Modes &md, const GridDesc &g, const Work &wk, double2 *h, hipStream_t st);
