@@ -692,11 +692,16 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
     // Items: a fixed stride over the tile-major list, the items of one walker
     // (one_per_walker), or the next free item from a counter (tickets): a
     // workgroup that finishes early takes more, and workgroups running
-    // together stay on neighbouring items of the list.  The next ticket is
-    // taken when an item starts and read by every thread after the item's
-    // last barrier, through two LDS slots used in turn (a slot is rewritten
-    // only two items later, after a barrier that every reader has passed),
-    // so no register holds it across the item.
+    // together stay on neighbouring items of the list.  With tickets, the
+    // first item of workgroup b is item b and the counter hands out items
+    // gridDim.x and up (had every workgroup drawn its first item from the
+    // counter, the first ones to start, which draw their second item as
+    // they begin the first, could take two items while later ones found
+    // none; with one walker's 245 items on 245 workgroups that doubled the
+    // kernel).  The next ticket is taken when an item starts and read by
+    // every thread after the item's last barrier, through two LDS slots used
+    // in turn (a slot is rewritten only two items later, after a barrier
+    // that every reader has passed), so no register holds it across the item.
     __shared__ int next_item[2];
     int par = 0;
     const bool tickets = !kWriteH && a.use_ticket && !a.one_per_walker;
@@ -706,13 +711,8 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
         end = min(a.wbase[blockIdx.x + 1], total);
         step = 1;
     }
-    if (tickets) {
-        if (threadIdx.x == 0) next_item[0] = atomicAdd(a.ticket, 1);
-        __syncthreads();
-        item = uni_i(next_item[0]);
-    }
     while (item < end) {
-        if (tickets && threadIdx.x == 0) next_item[par ^ 1] = atomicAdd(a.ticket, 1);
+        if (tickets && threadIdx.x == 0) next_item[par ^ 1] = (int)gridDim.x + atomicAdd(a.ticket, 1);
         // item values are wave-uniform: held in scalar registers, so that
         // none occupies a vector register across the item
         const int wk = a.one_per_walker ? (int)blockIdx.x : uni_i(a.item_w[item]);
