@@ -672,6 +672,7 @@ __device__ __forceinline__ void spline_solve(int wm, const GridDesc &g, bool act
             }
             A[r] = sub;
             Bm[r] = dia;
+            binv[r] = 1.0 / dia;
             C[r] = sup;
             for (int q = 0; q < G; ++q) {
                 const double *y = fn + ((size_t)wm * kNumFn + q0 + q) * ns;
@@ -679,11 +680,11 @@ __device__ __forceinline__ void spline_solve(int wm, const GridDesc &g, bool act
             }
         }
         __syncthreads();
-        // cyclic reduction rounds; each round first forms 1 / b of every
-        // row, one division per row instead of one per neighbour
+        // cyclic reduction rounds; each row's new b is stored with its
+        // reciprocal (one division per row instead of one per neighbour), and
+        // the last round stores M = d / b directly
         for (int s = 1; s < m; s *= 2) {
-            for (int r = threadIdx.x; r < m; r += kSplineThreads) binv[r] = 1.0 / Bm[r];
-            __syncthreads();
+            const bool last = 2 * s >= m;
             double na[kSplineRows], nb[kSplineRows], nc[kSplineRows], nd[kSplineRows][G];
 #pragma unroll
             for (int u = 0; u < kSplineRows; ++u) {
@@ -706,17 +707,25 @@ __device__ __forceinline__ void spline_solve(int wm, const GridDesc &g, bool act
             for (int u = 0; u < kSplineRows; ++u) {
                 const int r = threadIdx.x + u * kSplineThreads;
                 if (r >= m) continue;
-                A[r] = na[u];
-                Bm[r] = nb[u];
-                C[r] = nc[u];
+                if (last) {
+                    // M_{r+1} = d_r / b_r
 #pragma unroll
-                for (int q = 0; q < G; ++q) D[(size_t)q * m + r] = nd[u][q];
+                    for (int q = 0; q < G; ++q) D[(size_t)q * m + r] = nd[u][q] / nb[u];
+                } else {
+                    A[r] = na[u];
+                    Bm[r] = nb[u];
+                    binv[r] = 1.0 / nb[u];
+                    C[r] = nc[u];
+#pragma unroll
+                    for (int q = 0; q < G; ++q) D[(size_t)q * m + r] = nd[u][q];
+                }
             }
             __syncthreads();
         }
-        // M_{r+1} = d_r / b_r, in place
-        for (int t = threadIdx.x; t < G * m; t += kSplineThreads) D[t] /= Bm[t % m];
-        __syncthreads();
+        if (m == 1) {   // no reduction round: M_1 = d_0 / b_0
+            if (threadIdx.x < G) D[threadIdx.x] /= Bm[0];
+            __syncthreads();
+        }
         // end values from the not-a-knot conditions
         if (threadIdx.x < G) {
             const double *Mq = D + (size_t)threadIdx.x * m;   // Mq[r] = M_{r+1}
