@@ -809,11 +809,15 @@ __global__ __launch_bounds__(kSplineThreads) void k_sparse(const double *__restr
     if (a.done) {
         // one walker: the last of its mode workgroups to have its band builds
         // the work-item list, while the others go on with their knots
-        __threadfence();                           // this workgroup's band and source before the count
-        if (threadIdx.x == 0) last = atomicAdd(a.done, 1) == md.nm - 1;
+        // (thread 0 wrote this workgroup's band and source, and it alone
+        // reads the other modes' bands in items_one, so it alone fences)
+        if (threadIdx.x == 0) {
+            __threadfence();                       // this workgroup's band and source before the count
+            last = atomicAdd(a.done, 1) == md.nm - 1;
+            if (last) __threadfence();             // every mode's band after the count
+        }
         __syncthreads();
         if (last) {
-            __threadfence();                       // every mode's band after the count
             items_one(md.nm, g, a.src, a.band, a.wband, a.wbase, a.tile_off, a.ticket, a.item_w, a.item_t,
                       a.max_items);
             if (threadIdx.x == 0) *a.done = 0;
