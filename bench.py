@@ -56,7 +56,7 @@ LANE_OPS_PEAK = 3.93216e13
 # bin (the kernel's arithmetic), each uniform within one unit roundoff.
 SIG_REL_FP32C = 2.0 ** -24 * math.sqrt(29.0 / 3.0)
 BYTES_PER_WALKER_BIN = 72          # d (3 x complex128) + w (3 x float64), read once per walker
-KERNEL_REV = "dense-v24"           # traffic counters are only reused for this kernel revision
+KERNEL_REV = "dense-v25"           # traffic counters are only reused for this kernel revision
 
 
 def parse():
