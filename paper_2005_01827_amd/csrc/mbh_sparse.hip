@@ -587,6 +587,7 @@ __device__ __forceinline__ int first_bin(double x, double df)
 }
 
 constexpr int kSplineThreads = 256;
+constexpr int kThomasRows = 16;    // rows per interleaved system left for the Thomas sweeps
 constexpr int kSplineRows = 4;     // rows per thread: ns - 2 <= 1024
 
 // LDS of one spline workgroup solving G functions together: the matrix
@@ -680,11 +681,16 @@ __device__ __forceinline__ void spline_solve(int wm, const GridDesc &g, bool act
             }
         }
         __syncthreads();
-        // cyclic reduction rounds; each row's new b is stored with its
-        // reciprocal (one division per row instead of one per neighbour), and
-        // the last round stores M = d / b directly
-        for (int s = 1; s < m; s *= 2) {
-            const bool last = 2 * s >= m;
+        // Parallel cyclic reduction until the rows fall into P interleaved
+        // systems of at most about 16 rows (rows r = c, c + P, c + 2P, ...
+        // for c < P; P = 1 solves the whole system by one sweep), then one
+        // Thomas sweep per system: first the pivots and the modified upper
+        // diagonal, shared by the G functions, then the right-hand sides.
+        // Each row's new b is stored with its reciprocal (one division per
+        // row instead of one per neighbour).
+        int P = 1;
+        while (P * kThomasRows < m) P *= 2;
+        for (int s = 1; s < P; s *= 2) {
             double na[kSplineRows], nb[kSplineRows], nc[kSplineRows], nd[kSplineRows][G];
 #pragma unroll
             for (int u = 0; u < kSplineRows; ++u) {
@@ -707,25 +713,45 @@ __device__ __forceinline__ void spline_solve(int wm, const GridDesc &g, bool act
             for (int u = 0; u < kSplineRows; ++u) {
                 const int r = threadIdx.x + u * kSplineThreads;
                 if (r >= m) continue;
-                if (last) {
-                    // M_{r+1} = d_r / b_r
+                A[r] = na[u];
+                Bm[r] = nb[u];
+                binv[r] = 1.0 / nb[u];
+                C[r] = nc[u];
 #pragma unroll
-                    for (int q = 0; q < G; ++q) D[(size_t)q * m + r] = nd[u][q] / nb[u];
-                } else {
-                    A[r] = na[u];
-                    Bm[r] = nb[u];
-                    binv[r] = 1.0 / nb[u];
-                    C[r] = nc[u];
-#pragma unroll
-                    for (int q = 0; q < G; ++q) D[(size_t)q * m + r] = nd[u][q];
-                }
+                for (int q = 0; q < G; ++q) D[(size_t)q * m + r] = nd[u][q];
             }
             __syncthreads();
         }
-        if (m == 1) {   // no reduction round: M_1 = d_0 / b_0
-            if (threadIdx.x < G) D[threadIdx.x] /= Bm[0];
-            __syncthreads();
+        // After the rounds with s < P, row r couples only to r - P and r + P,
+        // and A[r] = 0 for r < P, C[r] = 0 for r >= m - P.  Forward sweep of
+        // system c: pivot 1 / (b - a c'_prev) into binv, c' into C.
+        if (threadIdx.x < P) {
+            double cp = 0.0;
+            for (int r = threadIdx.x; r < m; r += P) {
+                const double rd = 1.0 / (Bm[r] - A[r] * cp);
+                cp = C[r] * rd;
+                C[r] = cp;
+                binv[r] = rd;
+            }
         }
+        __syncthreads();
+        // right-hand sides forward, then back substitution: M_{r+1} in D
+        for (int t = threadIdx.x; t < P * G; t += kSplineThreads) {
+            const int c = t % P, q = t / P;
+            double *dq = D + (size_t)q * m;
+            double dp = 0.0;
+            int r = c;
+            for (; r < m; r += P) {
+                dp = (dq[r] - A[r] * dp) * binv[r];
+                dq[r] = dp;
+            }
+            double xv = dp;
+            for (r -= 2 * P; r >= c; r -= P) {
+                xv = dq[r] - C[r] * xv;
+                dq[r] = xv;
+            }
+        }
+        __syncthreads();
         // end values from the not-a-knot conditions
         if (threadIdx.x < G) {
             const double *Mq = D + (size_t)threadIdx.x * m;   // Mq[r] = M_{r+1}
