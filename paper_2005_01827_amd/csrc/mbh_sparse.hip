@@ -593,8 +593,10 @@ constexpr int kSplineRows = 4;     // rows per thread: ns - 2 <= 1024
 // LDS of one spline workgroup solving G functions together: the matrix
 // (3 m) and the reciprocals of its diagonal (m), G right-hand sides, 2 G end
 // values, the knots, the reciprocal interval widths and the knots' first
-// dense bins.
-constexpr size_t kSplineLdsMax = 65536;
+// dense bins.  Kept 1 KB under 64 KB, which leaves room for the fused
+// kernel's static LDS (the walker constants, the band, the item-list band);
+// G does not change the arithmetic of any function, only how many share a pass.
+constexpr size_t kSplineLdsMax = 65536 - 1024;
 __host__ __device__ inline size_t spline_lds_for(int ns, int G)
 {
     const size_t m = (size_t)ns - 2;
