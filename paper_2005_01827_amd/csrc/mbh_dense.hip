@@ -996,6 +996,17 @@ __global__ void k_reduce(int B, GridDesc g, const Source *__restrict__ src, cons
     const int w = blockIdx.x;
     const int lane = threadIdx.x;
     if (w >= B) return;
+    // the walker's band, validity and prefix sums are read while the
+    // partials are summed (independent loads, one round trip for both)
+    const WalkerBand wb = wband[w];
+    const bool valid = src[w].valid != 0;
+    double p_lo[3], p_hi[3], p_n[3];
+    for (int c = 0; c < 3; ++c) {
+        const double *p = pre + (size_t)c * (g.n + 1);
+        p_n[c] = p[g.n];
+        p_lo[c] = wb.ntiles > 0 ? p[wb.klo - g.k0] : 0.0;
+        p_hi[c] = wb.ntiles > 0 ? p[wb.khi - g.k0 + 1] : 0.0;
+    }
     double acc[kPartials];
     for (int q = 0; q < kPartials; ++q) acc[q] = 0.0;
     const int b0 = wbase[w], b1 = wbase[w + 1];
@@ -1008,18 +1019,16 @@ __global__ void k_reduce(int B, GridDesc g, const Source *__restrict__ src, cons
     }
     if (lane != 0) return;
     double o[7];
-    if (!src[w].valid) {
+    if (!valid) {
         o[0] = -INFINITY;
         for (int q = 1; q < 7; ++q) o[q] = 0.0;
     } else {
-        const WalkerBand wb = wband[w];
         // residual form over the band (both precisions), data-only sum
         // outside it
         double dd_out = 0.0;
         for (int c = 0; c < 3; ++c) {
-            const double *p = pre + (size_t)c * (g.n + 1);
-            if (wb.ntiles > 0) dd_out += p[wb.klo - g.k0] + (p[g.n] - p[wb.khi - g.k0 + 1]);
-            else dd_out += p[g.n];
+            if (wb.ntiles > 0) dd_out += p_lo[c] + (p_n[c] - p_hi[c]);
+            else dd_out += p_n[c];
         }
         o[0] = -0.5 * (acc[0] + acc[1] + acc[2] + dd_out);
         for (int c = 0; c < 3; ++c) {
