@@ -720,7 +720,7 @@ def extra_precision(args, O, w):
                     "p99_abs_dlnL": float(np.quantile(d, 0.99)),
                     "near_injection_64": {"max_abs_dlnL": float(dn.max()), "median_abs_dlnL": float(np.median(dn))},
                     "model_sigma_rel_times_snr": SIG_REL_FP32C * snr,
-                    "survey_floor_3e-8_snr": 3e-8 * snr}
+                    "floor_3e-8_times_snr": 3e-8 * snr}
             if speed:
                 case["speed"] = speed
                 case["fp32c_over_fp64_speed"] = round(speed["fp32c"]["evals_per_s"] / speed["fp64"]["evals_per_s"], 3)
@@ -828,8 +828,8 @@ def main():
         sampler_comparison(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the batch is sharded per GPU by design "
-                                   "(see the design notes), and --gpus N > 1 is not measured"}))
+        print(json.dumps({"error": "libmbh runs on one GPU; splitting the batch over GPUs is a design only "
+                                   "(see the design notes), so --gpus N > 1 is not measured"}))
         sys.exit(2)
     import torch
     from paper_2005_01827_amd import inputs, mbh

@@ -20,9 +20,9 @@ from bin to bin, so that ln L carries an error of rms
     sigma_w = sigma_rel * sqrt( sum_k |r~_k|^2 H~_k^2 / 2 ),
 
 with r~ = (d - h) sqrt(w) and H~ = H sqrt(w).  Near the data (r ~ noise,
-|r~_k|^2 ~ 2) that is sigma_rel times about rho_H, the C25 floor of the
-survey scaled by the number of roundings (about 1.9e-5 at SNR 100, 1.9e-4
-at SNR 1000).  The test allows 6 sigma_w, plus the FP64 parity tolerance
+|r~_k|^2 ~ 2) that is sigma_rel times about rho_H: a floor of one FP32
+rounding times the SNR, scaled by the number of roundings (about 1.9e-5 at
+SNR 100, 1.9e-4 at SNR 1000).  The test allows 6 sigma_w, plus the FP64 parity tolerance
 1e-10 max(|ln L|, 1) of the sparse stage and phase, plus 1e-6 for the
 float-float sums.  sigma_w is computed per walker from the oracle's
 per-mode templates.
