@@ -20,6 +20,7 @@ Other modes (each prints its own JSON line):
   --snr-table                 per-mode SNRs of the Table II binaries (Table III), zero noise and in noise;
   --knot-study                ln L accuracy and speed against the number of sparse knots per mode;
   --points-study              time per likelihood against the number of frequency points (Fig. 3);
+  --flow-study                the learned proposal's kernels: forward / inverse passes and a training step;
   --calibrate-copy MIB        a plain device copy, for scaling the traffic counters.
 """
 from __future__ import annotations
@@ -117,6 +118,10 @@ def parse():
                     help="instead of the throughput line, time one likelihood against the number of frequency "
                          "points (T_obs = 2^18 .. 2^25 s, f up to 0.15 Hz): one walker, a 1024-walker batch, and the "
                          "FP64 oracle on one core; one JSON line")
+    ap.add_argument("--flow-study", action="store_true",
+                    help="instead of the throughput line, time the learned proposal's kernels (the flow of the "
+                         "sampler: 11 coordinates, 8 layers, 128 hidden units) for forward and inverse passes of "
+                         "51 to 16384 rows and for one training step of 4096 rows; one JSON line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) and exit; used to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -804,8 +809,50 @@ def cpu_baseline(args, O, w, data, psd, lnl, gpu_evals_per_s):
     return cb, float(err.max()), ctx
 
 
+def flow_study(args):
+    """Device time per call of the flow kernels, from HIP events on the
+    current stream around reps back-to-back calls."""
+    import torch
+    from paper_2005_01827_amd import inputs, mbh
+    dim, layers, hidden = 11, 8, 128
+    fl = mbh.Flow(dim, layers, hidden, 16384, perm=inputs.flow_perms(dim, layers, 1), seed=1)
+    fl.set_params(inputs.flow_params(fl.n_params, 0.15, 2))
+    gen = torch.Generator(device="cuda").manual_seed(3)
+
+    def timed(fn, reps=50):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return round(e0.elapsed_time(e1) * 1e3 / reps, 1)
+
+    res = {"forward_us": {}, "inverse_us": {}}
+    for n in (51, 153, 1024, 4096, 16384):
+        u = torch.randn(n, dim, device="cuda", generator=gen)
+        z, lq = torch.empty_like(u), torch.empty(n, device="cuda")
+        res["forward_us"][str(n)] = timed(lambda: fl.forward(u, out=(z, lq)))
+        res["inverse_us"][str(n)] = timed(lambda: fl.inverse(u, out=(z, lq)))
+    u = torch.randn(4096, dim, device="cuda", generator=gen)
+
+    def train_step():
+        fl.loss_grad(u, want_grad=False)
+        fl.adam(1e-4)
+    res["train_step_4096_us"] = timed(train_step, reps=20)
+    fl.close()
+    print(json.dumps({"metric": "flow kernel device time per call", "unit": "us", "n_gpus": 1, "dtype": "f32",
+                      "config": {"dim": dim, "layers": layers, "hidden": hidden, "params": int(fl.n_params)},
+                      **res}), flush=True)
+
+
 def main():
     args = parse()
+    if args.flow_study and args.gpus == 1:
+        flow_study(args)
+        return
     if args.points_study and args.gpus == 1:
         points_study(args)
         return
