@@ -60,6 +60,7 @@ constexpr double kEulerGamma = 0.5772156649015329;
 constexpr double kMfJoin = 0.008;
 constexpr double kMfCut = 0.2;
 constexpr double kLorentzHeight = 2.0;
+constexpr double kPiPowM16 = 0x1.a711c663294aap-1;   // pi^(-1/6), the double nearest
 
 __device__ bool params_ok(const double *p)
 {
@@ -118,14 +119,19 @@ __device__ double amp22(const Source &s, double f)
     return s.A0 * pow(s.M * f, -7.0 / 6.0) * (1.0 + kLorentzHeight * lor) / (1.0 + exp(u));
 }
 
-// d/df ln(f^2 A_22)
-__device__ double dlog_f2amp(const Source &s, double f)
+// d/df ln(f^2 A_22) in v and its own f-derivative in dv
+__device__ void dlog_f2amp(const Source &s, double f, double &v, double &dv)
 {
     const double u = (f - s.fRD) / s.fd;
     const double lor = 1.0 / (1.0 + u * u);
-    const double tail = 1.0 - 1.0 / (1.0 + exp(u));   // 1 - logistic cut-off
+    const double lg = 1.0 / (1.0 + exp(u));          // logistic cut-off
+    const double tail = 1.0 - lg;
     const double dlor = -2.0 * u * lor * lor / s.fd;
-    return 5.0 / (6.0 * f) + kLorentzHeight * dlor / (1.0 + kLorentzHeight * lor) - tail / s.fd;
+    const double den = 1.0 + kLorentzHeight * lor;
+    v = 5.0 / (6.0 * f) + kLorentzHeight * dlor / den - tail / s.fd;
+    const double ddlor = -2.0 / s.fd * (lor * lor / s.fd + 2.0 * u * lor * dlor);
+    dv = -5.0 / (6.0 * f * f) + kLorentzHeight * (ddlor * den - kLorentzHeight * dlor * dlor) / (den * den) -
+         tail * lg / (s.fd * s.fd);
 }
 
 // Leading-order coefficient of the time-domain mode h_lm ~ H_lm e^{-i m Phi}
@@ -162,60 +168,150 @@ __device__ void mode_at(const Source &s, int l, int m, double f, double &A, doub
     dph = a - s.al1;
 }
 
-__device__ double mode_time(const Source &s, int l, int m, double f)
+// t_lm(f) and its f-derivative (the second phase derivative of the (2,2)
+// mode at 2f/m, scaled); the value is formed exactly as the root search of
+// f_start needs it.
+__device__ void mode_time(const Source &s, int l, int m, double f, double &t, double &dt)
 {
     const double ft = 2.0 * f / m;
     double p, a, b;
     phase22_raw(s, ft, p, a, b);
-    return s.tcoal - (a - s.al1) / kTwoPi;
+    t = s.tcoal - (a - s.al1) / kTwoPi;
+    dt = -(2.0 / m) * b / kTwoPi;
 }
 
 // ---------------------------------------------------------------------------
-// Root brackets refined by a group of kRootLanes lanes of one wavefront.  Each
-// round places kRootLanes - 1 points evenly inside [lo, hi] (one per lane;
-// the last lane holds hi), keeps the sub-bracket in which the predicate
-// first holds, and stops once no double lies strictly inside, i.e. lo and hi
-// are adjacent doubles.  pred must be false at lo and true at hi; for a
-// predicate that switches once, the result is the smallest double at which
-// it holds, the pair that repeated halving also ends on, in a sixth of the
-// halving rounds (each round divides the bracket by kRootLanes, not 2).  All
-// lanes of a group must call it together with the same lo and hi; the group
-// is the aligned block of kRootLanes lanes containing the caller.
+// Roots by one whole wavefront.  g(x, v, d) sets v = g(x) and d = g'(x) of a
+// function that rises through its root; the predicate is g >= 0.  Every lane
+// of the wavefront calls wave_root together with the same lo and hi.
+//
+// The first round evaluates both ends (lanes 0 and 63) and 62 points between
+// them, log-spaced over a range wider than a factor 2 and evenly spaced
+// otherwise, and returns the end values in glo and ghi.  Only if
+// g(lo) < 0 <= g(hi) does the search go on: each later round keeps the
+// bracket [lo, hi] with the values and slopes at both ends, and samples
+//   - 48 lanes evenly over a window about the two Newton steps from the ends,
+//     twice as wide as their spread, when that window is under an eighth of
+//     the bracket (near the root the steps straddle it and their spread
+//     shrinks quadratically), with 16 lanes evenly over the bracket, the last
+//     at hi;
+//   - else 64 lanes evenly over the bracket, the last at hi.
+// The new bracket is the smallest sample where the predicate holds and the
+// largest sample below it where it does not.  The search stops once no
+// sample lies strictly inside, i.e. lo and hi are adjacent doubles (the even
+// lanes reach every gap of fewer than 16 doubles).  For a predicate that
+// switches once this is the pair that repeated halving ends on.  Each round
+// divides the bracket by at least 16; near the root the window cuts it by
+// far more, so a root takes about 5 rounds where even sampling took 11.
 // ---------------------------------------------------------------------------
-constexpr int kRootLanes = 64;
-static_assert(kRootLanes >= 2 && kRootLanes <= 64 && (kRootLanes & (kRootLanes - 1)) == 0, "group of 2..64 lanes");
+constexpr int kRootLanes = 64;                 // a root search occupies one wavefront
+constexpr int kRootWindow = 48;                // window lanes of a guided round
+
+// v of lane j (j the same in every lane)
+__device__ __forceinline__ double lane_value(double v, int j)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, j);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), j);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 template <typename F>
-__device__ void group_bracket(double &lo, double &hi, F pred)
+__device__ void wave_root(double &lo, double &hi, double &glo, double &ghi, F g)
 {
     typedef unsigned long long lanes_t;
     const int lane = threadIdx.x & 63;
-    const int gl = lane & (kRootLanes - 1);
-    const int base = lane - gl;
-    const lanes_t gmask = kRootLanes == 64 ? ~0ull : (1ull << (kRootLanes & 63)) - 1ull;
+    double x, v = 0.0, d = 0.0;
+    {
+        const bool wide = lo > 0.0 && hi > 2.0 * lo;
+        const double L = wide ? log(hi / lo) : 0.0;
+        const double t = (double)lane * (1.0 / 63.0);
+        x = lane == 0 ? lo : lane == 63 ? hi : wide ? lo * exp(L * t) : fma(hi - lo, t, lo);
+    }
+    const bool in0 = lane == 0 || lane == 63 || (x > lo && x < hi);
+    if (in0) g(x, v, d);
+    glo = lane_value(v, 0);
+    ghi = lane_value(v, 63);
+    if (!(glo < 0.0 && ghi >= 0.0)) return;
+    // lanes are in increasing x: the first hit, and the last miss before it
+    double gl, dl, gh, dh;
+    {
+        const bool hit = lane == 63 || (in0 && lane > 0 && v >= 0.0);
+        const int jh = __ffsll((lanes_t)__ballot(hit)) - 1;
+        const lanes_t miss = (lanes_t)__ballot(lane == 0 || (in0 && !(v >= 0.0))) & ((1ull << jh) - 1ull);
+        const int jl = 63 - __clzll(miss);
+        lo = lane_value(x, jl);
+        gl = lane_value(v, jl);
+        dl = lane_value(d, jl);
+        hi = lane_value(x, jh);
+        gh = lane_value(v, jh);
+        dh = lane_value(d, jh);
+    }
     for (int round = 0; round < 80; ++round) {
-        const double x = gl < kRootLanes - 1 ? fma(hi - lo, (double)(gl + 1) * (1.0 / kRootLanes), lo) : hi;
-        const bool inside = x > lo && x < hi;
-        const bool hit = inside && pred(x);
-        const lanes_t gi = ((lanes_t)__ballot(inside) >> base) & gmask;
-        const lanes_t gh = ((lanes_t)__ballot(hit) >> base) & gmask;
-        if (gi == 0ull) break;                     // lo and hi are adjacent
-        if (gh != 0ull) {
-            const int j = __ffsll(gh) - 1;         // first sample where pred holds
-            const lanes_t below = gi & ((1ull << j) - 1ull);
-            const double xj = __shfl(x, base + j);
-            const double xb = __shfl(x, base + (below ? 63 - __clzll(below) : 0));
-            if (below) lo = xb;
-            hi = xj;
+        const double W = hi - lo;
+        const double xa = dl > 0.0 ? lo - gl / dl : hi;
+        const double xb = dh > 0.0 ? hi - gh / dh : lo;
+        const double a = fmin(xa, xb), b = fmax(xa, xb);
+        const double c = 0.5 * (a + b);
+        const double hw = 2.0 * (b - a) + 0x1p-50 * fabs(c);
+        const bool win = hw < 0.125 * W && c > lo && c < hi;       // false for a NaN
+        const lanes_t wmask = win ? (1ull << kRootWindow) - 1ull : 0ull;
+        if (win && lane < kRootWindow) {
+            x = fma(hw, (double)(2 * lane + 1 - kRootWindow) * (1.0 / (kRootWindow + 1)), c);
         } else {
-            lo = __shfl(x, base + 63 - __clzll(gi));  // pred false at every sample
+            const int j = win ? lane - kRootWindow : lane;
+            const int last = win ? 63 - kRootWindow : 63;
+            x = j < last ? fma(W, (double)(j + 1) * (win ? 1.0 / (64 - kRootWindow) : 1.0 / 64), lo) : hi;
+        }
+        const bool inside = x > lo && x < hi;
+        if ((lanes_t)__ballot(inside) == 0ull) break;               // lo and hi are adjacent
+        v = 0.0;
+        d = 0.0;
+        if (inside) g(x, v, d);
+        const bool hit = inside && v >= 0.0;
+        // each part (window, even) is sorted: its first hit and last miss
+        const lanes_t hm = (lanes_t)__ballot(hit);
+        int jh = -1;
+        double nh = hi;
+        if (hm & wmask) {
+            const int j = __ffsll(hm & wmask) - 1;
+            const double xj = lane_value(x, j);
+            if (xj < nh) { nh = xj; jh = j; }
+        }
+        if (hm & ~wmask) {
+            const int j = __ffsll(hm & ~wmask) - 1;
+            const double xj = lane_value(x, j);
+            if (xj < nh) { nh = xj; jh = j; }
+        }
+        if (jh >= 0) {
+            hi = nh;
+            gh = lane_value(v, jh);
+            dh = lane_value(d, jh);
+        }
+        const lanes_t mm = (lanes_t)__ballot(inside && !hit && x < hi);
+        int jl = -1;
+        double nl = lo;
+        if (mm & wmask) {
+            const int j = 63 - __clzll(mm & wmask);
+            const double xj = lane_value(x, j);
+            if (xj > nl) { nl = xj; jl = j; }
+        }
+        if (mm & ~wmask) {
+            const int j = 63 - __clzll(mm & ~wmask);
+            const double xj = lane_value(x, j);
+            if (xj > nl) { nl = xj; jl = j; }
+        }
+        if (jl >= 0) {
+            lo = nl;
+            gl = lane_value(v, jl);
+            dl = lane_value(d, jl);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Per-walker constants (a1 and the alignment at f_peak), from the 11
-// parameters at p.  Called by a whole group of kRootLanes lanes, which share
+// parameters at p.  Called by a whole wavefront, whose lanes share
 // the root search for f_peak; every lane returns the same value.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ Source source_of(const double *__restrict__ p, double t0)
@@ -288,30 +384,32 @@ __device__ __forceinline__ Source source_of(const double *__restrict__ p, double
     s.b1 = d1j - s.cR * pow(s.fJ, -8.0 / 3.0) + s.kRD * atan(uj);
     s.b0 = pj - s.b1 * s.fJ + 0.6 * s.cR * pow(s.fJ, -5.0 / 3.0) + s.kRD * s.fd * (uj * atan(uj) - 0.5 * log1p(uj * uj));
 
-    // f_peak: bisection of d ln(f^2 A_22)/df on [f_J, f_RD]
-    double lo = s.fJ, hi = s.fRD, fp;
-    if (dlog_f2amp(s, lo) <= 0.0) {
-        fp = lo;
-    } else if (dlog_f2amp(s, hi) >= 0.0) {
-        fp = hi;
-    } else {
-        group_bracket(lo, hi, [&](double x) { return dlog_f2amp(s, x) <= 0.0; });
-        fp = 0.5 * (lo + hi);
-    }
+    // f_peak: root of d ln(f^2 A_22)/df on [f_J, f_RD], bracketed to adjacent
+    // doubles (the root search takes g = -d ln(f^2 A_22)/df, which rises)
+    double lo = s.fJ, hi = s.fRD, glo, ghi, fp;
+    wave_root(lo, hi, glo, ghi, [&](double x, double &v, double &dv) {
+        dlog_f2amp(s, x, v, dv);
+        v = -v;
+        dv = -dv;
+    });
+    if (glo >= 0.0) fp = s.fJ;                     // the slope is already <= 0 at f_J
+    else if (ghi <= 0.0) fp = s.fRD;               // still >= 0 at f_RD
+    else fp = 0.5 * (lo + hi);
     s.fpeak = fp;
     double a, b, c;
     phase22_raw(s, fp, a, b, c);
     s.al0 = a;
     s.al1 = b;
-    s.A0 = sqrt(2.0 * eta / 3.0) * pow(kPi, -1.0 / 6.0) * s.M * s.M / s.Dl;    return s;
+    s.A0 = sqrt(2.0 * eta / 3.0) * kPiPowM16 * s.M * s.M / s.Dl;
+    return s;
 }
 
-// Kernel 1: one group of kRootLanes lanes per walker (lane 0 of the group writes).
+// Kernel 1: one wavefront per walker (its lane 0 writes).
 __global__ __launch_bounds__(128) void k_source(const double *__restrict__ params, int B, double t0, Source *__restrict__ out)
 {
     const int w = (blockIdx.x * blockDim.x + threadIdx.x) / kRootLanes;
     const bool writer = (threadIdx.x & (kRootLanes - 1)) == 0;
-    if (w >= B) return;                            // whole groups leave together
+    if (w >= B) return;                            // whole wavefronts leave together
     const Source s = source_of(params + 11 * (size_t)w, t0);
     if (writer) out[w] = s;
 }
@@ -339,11 +437,11 @@ __device__ void swsh_m2(int l, int m, double th, double ph, double &re, double &
 }
 
 // ---------------------------------------------------------------------------
-// Frequency support and polarization weights of mode (l, m) (a3), called by a
-// whole group of kRootLanes lanes.  f_start is the root of t_lm(f) = 0,
-// bracketed to adjacent doubles; f_end = min(band end, (m/2) 0.2 / M).
+// Frequency support of mode (l, m) (a3), called by a whole wavefront; the
+// weights are left zero.  f_start is the root of t_lm(f) = 0, bracketed to
+// adjacent doubles; f_end = min(band end, (m/2) 0.2 / M).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ ModeBand band_of(const Source &s, int l, int m, const GridDesc &g)
+__device__ __forceinline__ ModeBand band_support(const Source &s, int l, int m, const GridDesc &g)
 {
     ModeBand b;
     b.fs = 0.0;
@@ -362,15 +460,11 @@ __device__ __forceinline__ ModeBand band_of(const Source &s, int l, int m, const
         bool have = fe > f_lo;
         double fs = f_lo;
         if (have) {
-            if (mode_time(s, l, m, f_lo) >= 0.0) {
-                fs = f_lo;
-            } else if (mode_time(s, l, m, fe) < 0.0) {
-                have = false;
-            } else {
-                double lo = f_lo, hi = fe;
-                group_bracket(lo, hi, [&](double x) { return mode_time(s, l, m, x) >= 0.0; });
-                fs = hi;
-            }
+            double lo = f_lo, hi = fe, glo, ghi;
+            wave_root(lo, hi, glo, ghi, [&](double x, double &t, double &dt) { mode_time(s, l, m, x, t, dt); });
+            if (glo >= 0.0) fs = f_lo;                 // the mode starts before the band
+            else if (ghi < 0.0) have = false;          // ... or only after its end
+            else fs = hi;
         }
         if (have) {
             b.fs = fs;
@@ -382,25 +476,40 @@ __device__ __forceinline__ ModeBand band_of(const Source &s, int l, int m, const
             b.khi = (int)khi;
             b.active = (khi >= klo + 3) ? 1 : 0;
         }
-        // K+ = (Y_{l,-m} + (-1)^l conj Y_{lm}) / 2,  Kx = i (Y_{l,-m} - (-1)^l conj Y_{lm}) / 2
-        double ar, ai, br, bi;
-        swsh_m2(l, -m, s.iota, s.phiref, ar, ai);
-        swsh_m2(l, m, s.iota, s.phiref, br, bi);
-        bi = -bi;
-        const double sg = (l & 1) ? -1.0 : 1.0;
-        b.kp[0] = 0.5 * (ar + sg * br);
-        b.kp[1] = 0.5 * (ai + sg * bi);
-        const double dr = ar - sg * br, di = ai - sg * bi;
-        b.kc[0] = -0.5 * di;
-        b.kc[1] = 0.5 * dr;
-    }    return b;
+    }
+    return b;
 }
 
-// Kernel 2: one group of kRootLanes lanes per (walker, mode).
+// Plus and cross weights of mode (l, m) (complex, re and im), which depend
+// only on the inclination and phi_ref:
+//   K+ = (Y_{l,-m} + (-1)^l conj Y_{lm}) / 2,  Kx = i (Y_{l,-m} - (-1)^l conj Y_{lm}) / 2.
+__device__ void mode_weights(int l, int m, double iota, double phiref, double (&kp)[2], double (&kc)[2])
+{
+    double ar, ai, br, bi;
+    swsh_m2(l, -m, iota, phiref, ar, ai);
+    swsh_m2(l, m, iota, phiref, br, bi);
+    bi = -bi;
+    const double sg = (l & 1) ? -1.0 : 1.0;
+    kp[0] = 0.5 * (ar + sg * br);
+    kp[1] = 0.5 * (ai + sg * bi);
+    const double dr = ar - sg * br, di = ai - sg * bi;
+    kc[0] = -0.5 * di;
+    kc[1] = 0.5 * dr;
+}
+
+// Band and weights of mode (l, m) (a3), by one wavefront.
+__device__ __forceinline__ ModeBand band_of(const Source &s, int l, int m, const GridDesc &g)
+{
+    ModeBand b = band_support(s, l, m, g);
+    if (s.valid) mode_weights(l, m, s.iota, s.phiref, b.kp, b.kc);
+    return b;
+}
+
+// Kernel 2: one wavefront per (walker, mode).
 __global__ __launch_bounds__(64) void k_bands(int B, Modes md, GridDesc g, const Source *__restrict__ src, ModeBand *__restrict__ band)
 {
     const int id = (blockIdx.x * blockDim.x + threadIdx.x) / kRootLanes;
-    if (id >= B * md.nm) return;                   // whole groups leave together
+    if (id >= B * md.nm) return;                   // whole wavefronts leave together
     const int w = id / md.nm, im = id - w * md.nm;
     const Source s = src[w];
     const ModeBand b = band_of(s, md.l[im], md.m[im], g);
@@ -589,6 +698,7 @@ __device__ __forceinline__ int first_bin(double x, double df)
 constexpr int kSplineThreads = 256;
 constexpr int kThomasRows = 16;    // rows per interleaved system left for the Thomas sweeps
 constexpr int kSplineRows = 4;     // rows per thread: ns - 2 <= 1024
+constexpr int kCoefChunk = 8;      // coefficient items per thread whose loads are issued together
 
 // LDS of one spline workgroup solving G functions together: the matrix
 // (3 m) and the reciprocals of its diagonal (m), G right-hand sides, 2 G end
@@ -684,7 +794,7 @@ __device__ __forceinline__ void spline_solve(int wm, const GridDesc &g, bool act
         }
         __syncthreads();
         // Parallel cyclic reduction until the rows fall into P interleaved
-        // systems of at most about 16 rows (rows r = c, c + P, c + 2P, ...
+        // systems of at most kThomasRows rows (rows r = c, c + P, c + 2P, ...
         // for c < P; P = 1 solves the whole system by one sweep), then one
         // Thomas sweep per system: first the pivots and the modified upper
         // diagonal, shared by the G functions, then the right-hand sides.
@@ -696,44 +806,74 @@ __device__ __forceinline__ void spline_solve(int wm, const GridDesc &g, bool act
             double na[kSplineRows], nb[kSplineRows], nc[kSplineRows], nd[kSplineRows][G];
 #pragma unroll
             for (int u = 0; u < kSplineRows; ++u) {
-                const int r = threadIdx.x + u * kSplineThreads;
-                if (r >= m) continue;
-                const bool lo = r - s >= 0, hi = r + s < m;
-                const double al = lo ? -A[r] * binv[r - s] : 0.0;
-                const double ga = hi ? -C[r] * binv[r + s] : 0.0;
-                na[u] = lo ? al * A[r - s] : 0.0;
-                nc[u] = hi ? ga * C[r + s] : 0.0;
-                nb[u] = Bm[r] + (lo ? al * C[r - s] : 0.0) + (hi ? ga * A[r + s] : 0.0);
+                if (u * kSplineThreads < m) {
+                    // neighbour indices clamped into the system, so that every
+                    // load of the round is issued at once, with no branch; a
+                    // missing neighbour gets a zero factor (rows past m repeat
+                    // row m - 1 and are not stored)
+                    const int r = min((int)threadIdx.x + u * kSplineThreads, m - 1);
+                    const int rl = max(r - s, 0), rh = min(r + s, m - 1);
+                    const double Ar = A[r], Cr = C[r], Br = Bm[r];
+                    const double bl = binv[rl], bh = binv[rh];
+                    const double Al = A[rl], Cl = C[rl], Ah = A[rh], Ch = C[rh];
+                    double dr[G], dl[G], dh[G];
 #pragma unroll
-                for (int q = 0; q < G; ++q) {
-                    const double *dq = D + (size_t)q * m;
-                    nd[u][q] = dq[r] + (lo ? al * dq[r - s] : 0.0) + (hi ? ga * dq[r + s] : 0.0);
+                    for (int q = 0; q < G; ++q) {
+                        const double *dq = D + (size_t)q * m;
+                        dr[q] = dq[r];
+                        dl[q] = dq[rl];
+                        dh[q] = dq[rh];
+                    }
+                    const double al = r - s >= 0 ? -Ar * bl : 0.0;
+                    const double ga = r + s < m ? -Cr * bh : 0.0;
+                    na[u] = al * Al;
+                    nc[u] = ga * Ch;
+                    nb[u] = Br + al * Cl + ga * Ah;
+#pragma unroll
+                    for (int q = 0; q < G; ++q) nd[u][q] = dr[q] + al * dl[q] + ga * dh[q];
                 }
             }
             __syncthreads();
 #pragma unroll
             for (int u = 0; u < kSplineRows; ++u) {
                 const int r = threadIdx.x + u * kSplineThreads;
-                if (r >= m) continue;
-                A[r] = na[u];
-                Bm[r] = nb[u];
-                binv[r] = 1.0 / nb[u];
-                C[r] = nc[u];
+                if (r < m) {
+                    A[r] = na[u];
+                    Bm[r] = nb[u];
+                    binv[r] = 1.0 / nb[u];
+                    C[r] = nc[u];
 #pragma unroll
-                for (int q = 0; q < G; ++q) D[(size_t)q * m + r] = nd[u][q];
+                    for (int q = 0; q < G; ++q) D[(size_t)q * m + r] = nd[u][q];
+                }
             }
             __syncthreads();
         }
         // After the rounds with s < P, row r couples only to r - P and r + P,
         // and A[r] = 0 for r < P, C[r] = 0 for r >= m - P.  Forward sweep of
         // system c: pivot 1 / (b - a c'_prev) into binv, c' into C.
-        if (threadIdx.x < P) {
+        // Each system has at most kThomasRows rows (P kThomasRows >= m); its
+        // rows are read into registers first, so that the sweeps wait on no
+        // load.
+        if ((int)threadIdx.x < P) {
+            const int c = threadIdx.x;
+            double bv[kThomasRows], av[kThomasRows], cv[kThomasRows];
+#pragma unroll
+            for (int k = 0; k < kThomasRows; ++k) {
+                const int r = min(c + k * P, m - 1);
+                bv[k] = Bm[r];
+                av[k] = A[r];
+                cv[k] = C[r];
+            }
             double cp = 0.0;
-            for (int r = threadIdx.x; r < m; r += P) {
-                const double rd = 1.0 / (Bm[r] - A[r] * cp);
-                cp = C[r] * rd;
-                C[r] = cp;
-                binv[r] = rd;
+#pragma unroll
+            for (int k = 0; k < kThomasRows; ++k) {
+                const int r = c + k * P;
+                if (r < m) {
+                    const double rd = 1.0 / (bv[k] - av[k] * cp);
+                    cp = cv[k] * rd;
+                    C[r] = cp;
+                    binv[r] = rd;
+                }
             }
         }
         __syncthreads();
@@ -741,16 +881,31 @@ __device__ __forceinline__ void spline_solve(int wm, const GridDesc &g, bool act
         for (int t = threadIdx.x; t < P * G; t += kSplineThreads) {
             const int c = t % P, q = t / P;
             double *dq = D + (size_t)q * m;
-            double dp = 0.0;
-            int r = c;
-            for (; r < m; r += P) {
-                dp = (dq[r] - A[r] * dp) * binv[r];
-                dq[r] = dp;
+            const int nr = (m - c + P - 1) / P;            // rows of system c
+            double dv[kThomasRows], av[kThomasRows], bi[kThomasRows], cv[kThomasRows];
+#pragma unroll
+            for (int k = 0; k < kThomasRows; ++k) {
+                const int r = min(c + k * P, m - 1);
+                dv[k] = dq[r];
+                av[k] = A[r];
+                bi[k] = binv[r];
+                cv[k] = C[r];
             }
-            double xv = dp;
-            for (r -= 2 * P; r >= c; r -= P) {
-                xv = dq[r] - C[r] * xv;
-                dq[r] = xv;
+            double dp = 0.0;
+#pragma unroll
+            for (int k = 0; k < kThomasRows; ++k) {
+                if (k < nr) {
+                    dp = (dv[k] - av[k] * dp) * bi[k];
+                    dv[k] = dp;
+                }
+            }
+            double xv = 0.0;                               // the last row keeps its forward value
+#pragma unroll
+            for (int k = kThomasRows - 1; k >= 0; --k) {
+                if (k < nr) {
+                    xv = dv[k] - cv[k] * xv;
+                    dq[c + k * P] = xv;
+                }
             }
         }
         __syncthreads();
@@ -763,25 +918,51 @@ __device__ __forceinline__ void spline_solve(int wm, const GridDesc &g, bool act
             M1[threadIdx.x] = ((ha + hb) * Mq[m - 1] - hb * Mq[m - 2]) / ha;
         }
         __syncthreads();
-        // coefficients of interval i from knots i, i+1, re-centred on fc
-        for (int t = threadIdx.x; t < (ns - 1) * G; t += kSplineThreads) {
-            const int i = t / G, q = t % G;
-            const double *Mq = D + (size_t)q * m;
-            const double *y = fn + ((size_t)wm * kNumFn + q0 + q) * ns;
-            const double mi = i == 0 ? M0[q] : Mq[i - 1];
-            const double mj = i + 1 == ns - 1 ? M1[q] : Mq[i];
-            const double x0 = x[i], h = x[i + 1] - x0, hi = hinv[i];
-            const double sl = (y[i + 1] - y[i]) * hi;
-            const double p0 = y[i], p1 = sl - h * (2.0 * mi + mj) / 6.0, p2 = 0.5 * mi, p3 = (mj - mi) * hi / 6.0;
-            const double dl = (double)kbl[i + 1] * g.df - x0;
-            double *o = out + (size_t)i * kCoefPerIv + (q0 + q) * 4;
-            o[0] = fma(fma(fma(p3, dl, p2), dl, p1), dl, p0);
-            o[1] = fma(fma(3.0 * p3, dl, 2.0 * p2), dl, p1);
-            o[2] = fma(3.0 * p3, dl, p2);
-            o[3] = p3;
+        // coefficients of interval i from knots i, i+1, re-centred on fc, one
+        // (interval, function) item per thread and pass (the function index
+        // fastest, so that a wavefront's stores are contiguous); every load
+        // of a thread's kCoefChunk items is issued before the first is used
+        const int nt = (ns - 1) * G;
+        for (int t0 = 0; t0 < nt; t0 += kCoefChunk * kSplineThreads) {
+            double ya[kCoefChunk], yb[kCoefChunk], mi[kCoefChunk], mj[kCoefChunk];
+            double xa[kCoefChunk], xb[kCoefChunk], hv[kCoefChunk];
+            int kb[kCoefChunk];
+#pragma unroll
+            for (int k = 0; k < kCoefChunk; ++k) {
+                const int t = min(t0 + (int)threadIdx.x + k * kSplineThreads, nt - 1);
+                const int i = t / G, q = t % G;
+                const double *y = fn + ((size_t)wm * kNumFn + q0 + q) * ns;
+                const double *Mq = D + (size_t)q * m;
+                ya[k] = y[i];
+                yb[k] = y[i + 1];
+                mi[k] = i == 0 ? M0[q] : Mq[max(i - 1, 0)];
+                mj[k] = i + 1 == ns - 1 ? M1[q] : Mq[min(i, m - 1)];
+                xa[k] = x[i];
+                xb[k] = x[i + 1];
+                hv[k] = hinv[i];
+                kb[k] = kbl[i + 1];
+            }
+#pragma unroll
+            for (int k = 0; k < kCoefChunk; ++k) {
+                const int t = t0 + (int)threadIdx.x + k * kSplineThreads;
+                if (t < nt) {
+                    const int i = t / G, q = t % G;
+                    const double h = xb[k] - xa[k], hi = hv[k];
+                    const double sl = (yb[k] - ya[k]) * hi;
+                    const double p0 = ya[k], p1 = sl - h * (1.0 / 6.0) * (2.0 * mi[k] + mj[k]), p2 = 0.5 * mi[k];
+                    const double p3 = (mj[k] - mi[k]) * hi * (1.0 / 6.0);
+                    const double dl = (double)kb[k] * g.df - xa[k];
+                    double *o = out + (size_t)i * kCoefPerIv + (q0 + q) * 4;
+                    o[0] = fma(fma(fma(p3, dl, p2), dl, p1), dl, p0);
+                    o[1] = fma(fma(3.0 * p3, dl, 2.0 * p2), dl, p1);
+                    o[2] = fma(3.0 * p3, dl, p2);
+                    o[3] = p3;
+                }
+            }
         }
         __syncthreads();
-    }}
+    }
+}
 
 // Kernel 5: one workgroup per (walker, mode).
 template <int G>
@@ -813,6 +994,7 @@ __global__ __launch_bounds__(kSplineThreads) void k_sparse(const double *__restr
     extern __shared__ double sm[];
     __shared__ Source ss;
     __shared__ ModeBand sb;
+    __shared__ double swt[4];                      // the mode's K+ and Kx
     __shared__ int last;
     const int wm = blockIdx.x;
     if (wm >= B * md.nm) return;                   // whole workgroups leave together
@@ -824,10 +1006,27 @@ __global__ __launch_bounds__(kSplineThreads) void k_sparse(const double *__restr
             ss = s;
             if (im == 0) a.src[w] = s;
         }
+    } else if (threadIdx.x < 2 * kRootLanes) {
+        // the mode's weights need only the inclination and phi_ref: the
+        // second wavefront forms them while the first finds f_peak and f_start
+        double kp[2], kc[2];
+        mode_weights(l, m, params[11 * (size_t)w + 6], params[11 * (size_t)w + 5], kp, kc);
+        if (threadIdx.x == kRootLanes) {
+            swt[0] = kp[0];
+            swt[1] = kp[1];
+            swt[2] = kc[0];
+            swt[3] = kc[1];
+        }
     }
     __syncthreads();
     if (threadIdx.x < kRootLanes) {
-        const ModeBand b = band_of(ss, l, m, g);
+        ModeBand b = band_support(ss, l, m, g);
+        if (ss.valid) {
+            b.kp[0] = swt[0];
+            b.kp[1] = swt[1];
+            b.kc[0] = swt[2];
+            b.kc[1] = swt[3];
+        }
         if (threadIdx.x == 0) {
             sb = b;
             a.band[wm] = b;
@@ -892,7 +1091,7 @@ hipError_t launch_waveform(const double *params, int B, const Modes &md, const G
                            hipStream_t st)
 {
     if (B <= 0) return hipSuccess;
-    // kRootLanes lanes per walker and per (walker, mode)
+    // one wavefront per walker and per (walker, mode)
     constexpr int kPerBlock = 64 / kRootLanes;
     k_source<<<(unsigned)((B + 2 * kPerBlock - 1) / (2 * kPerBlock)), 128, 0, st>>>(params, B, g.t0, wk.src);
     const int nb = B * md.nm;

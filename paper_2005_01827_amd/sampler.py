@@ -181,6 +181,19 @@ def batch_means_se(chain: np.ndarray, n_batches: int = 20) -> np.ndarray:
     return means.std(axis=0, ddof=1) / math.sqrt(nb)
 
 
+def ensemble_mean_se(chain: np.ndarray, c_window: float = 5.0) -> np.ndarray:
+    """Standard error of the ensemble mean of chain[N, W, D] per parameter,
+    from the integrated autocorrelation time of the series of ensemble means
+    (the Sokal window above): sqrt(var(m) tau_m / N).  It needs no choice of
+    batch length, which biases batch means low when a batch spans only a few
+    autocorrelation times of the ensemble as a whole."""
+    x = np.asarray(chain, dtype=np.float64)
+    m = x.mean(axis=1)                                        # [N][D]
+    n = m.shape[0]
+    taus = np.array([integrated_time(m[:, d:d + 1], c_window) for d in range(m.shape[1])])
+    return m.std(axis=0) * np.sqrt(np.maximum(taus, 1.0) / n)
+
+
 def ess(chain: np.ndarray, c_window: float = 5.0):
     """Effective sample size of chain[N, W, D]: N W / max_d tau_d.
     Returns (ess, tau_max, taus)."""

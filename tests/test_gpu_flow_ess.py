@@ -114,7 +114,12 @@ def _compare_pt(loglike, logprior, x0, betas, burn, steps, fit_kwargs, a=1.15, p
     acc = fl.state.flow_accepted / max(1, fl.state.flow_proposed)
     a1, a2 = ch_b.reshape(-1, DIM), ch_f.reshape(-1, DIM)
     se_b, se_f = S.batch_means_se(ch_b), S.batch_means_se(ch_f)
-    z = float(np.max(np.abs(a1.mean(0) - a2.mean(0)) / np.sqrt(se_b ** 2 + se_f ** 2)))
+    # equal accuracy: each arm's standard error is the larger of its batch
+    # means (20 batches, a few autocorrelation times of the ensemble mean
+    # each, which bias it low) and its autocorrelation estimate
+    ue_b = np.maximum(se_b, S.ensemble_mean_se(ch_b))
+    ue_f = np.maximum(se_f, S.ensemble_mean_se(ch_f))
+    z = float(np.max(np.abs(a1.mean(0) - a2.mean(0)) / np.sqrt(ue_b ** 2 + ue_f ** 2)))
     sd = float(np.max(np.abs(a2.std(0) / a1.std(0) - 1)))
     # batch-means ESS of the ensemble mean per parameter; the median over
     # parameters is the gain statistic (the minimum swings by several times

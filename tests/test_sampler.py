@@ -80,6 +80,34 @@ def test_batch_means_standard_error():
     assert np.all(se_y > 3 * naive)
 
 
+def test_ensemble_mean_standard_error():
+    """The autocorrelation estimate of the ensemble mean's standard error on
+    independent AR(1) walkers, whose ensemble mean is AR(1) with the same
+    coefficient: sqrt(tau / (N W)) per unit variance, tau = (1 + r) / (1 - r);
+    and on walkers that share one slow AR(1) component, where it exceeds the
+    walker-averaged figure as the batch means do."""
+    rng = np.random.default_rng(9)
+    r, n, w = 0.8, 20000, 32
+    e = rng.standard_normal((n, w, 3))
+    x = np.empty_like(e)
+    x[0] = e[0]
+    for t in range(1, n):
+        x[t] = r * x[t - 1] + math.sqrt(1 - r * r) * e[t]
+    se = S.ensemble_mean_se(x)
+    want = math.sqrt((1 + r) / (1 - r) / (n * w))
+    assert np.all(np.abs(se / want - 1) < 0.15), se / want
+    c = np.empty(n)
+    c[0] = 0.0
+    g = rng.standard_normal(n)
+    for t in range(1, n):
+        c[t] = 0.99 * c[t - 1] + math.sqrt(1 - 0.99 ** 2) * g[t]
+    y = x + 0.3 * c[:, None, None]
+    # shared part: variance 0.09, tau = 1.99 / 0.01; own part as above
+    want_y = math.sqrt((0.09 * 199.0 + (1 + r) / (1 - r) / w) / n)
+    se_y = S.ensemble_mean_se(y)
+    assert np.all(np.abs(se_y / want_y - 1) < 0.35), se_y / want_y
+
+
 def test_stretch_move_recovers_correlated_gaussian():
     dim = 11
     mu, cov, ll = _gauss_target(dim, 3)
