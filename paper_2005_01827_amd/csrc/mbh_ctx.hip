@@ -173,11 +173,13 @@ mbh_status enqueue_all(mbh_ctx *c, const double *params, int B, double *out7, do
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     hipError_t e;
-    // small batches: the sparse stage as one kernel (with one walker also
-    // the work-item list); larger ones: one kernel per step
+    // small batches: the sparse stage as one kernel; larger ones: one kernel
+    // per step.  One walker (tickets) needs no item list: the sparse kernel
+    // zeroes the counter and the dense kernel takes the walker's tiles.
     const bool fused = B <= kFusedSparseMaxBatch;
+    const bool one = fused && B == 1 && !c->sch.one_per_walker;
     if (fused) {
-        if ((e = launch_sparse(params, B, c->md, c->g, c->wk, c->max_items, true, st)) != hipSuccess)
+        if ((e = launch_sparse(params, B, c->md, c->g, c->wk, one, st)) != hipSuccess)
             return hip_fail(c, e, "sparse");
     } else {
         if ((e = launch_waveform(params, B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "waveform");
@@ -186,8 +188,8 @@ mbh_status enqueue_all(mbh_ctx *c, const double *params, int B, double *out7, do
     }
     if ((e = launch_coef32(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "coef32");
     if ((e = launch_walker_bands(B, c->md, c->g, c->wk, st)) != hipSuccess) return hip_fail(c, e, "bands");
-    if ((e = launch_dense(B, c->md, c->g, c->wk, data_of(c), c->max_items, c->sch, false, st, ev0, ev1,
-                          fused && B == 1)) != hipSuccess)
+    if ((e = launch_dense(B, c->md, c->g, c->wk, data_of(c), c->max_items, c->sch, false, st, ev0, ev1, one)) !=
+        hipSuccess)
         return hip_fail(c, e, "dense");
     if ((e = launch_reduce(B, c->g, c->wk, data_of(c), out7, logL, st)) != hipSuccess) return hip_fail(c, e, "reduce");
     return MBH_OK;
@@ -376,7 +378,6 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
     TRY(dalloc(c, &c->wk.item_t, (size_t)c->max_items));
     TRY(dalloc(c, &c->wk.tile_off, (size_t)ntile_max + 1));
     TRY(dalloc(c, &c->wk.ticket, (size_t)64));
-    TRY(dalloc(c, &c->wk.done, (size_t)1));
     TRY(dalloc(c, &c->wk.wbase, (size_t)B + 1));
     TRY(dalloc(c, &c->wk.partial, (size_t)c->max_items * kPartials));
     TRY(dalloc(c, &c->wk.out7, (size_t)B * 7));
@@ -400,7 +401,6 @@ mbh_status mbh_ctx_create(const mbh_ctx_desc *desc, mbh_ctx **out)
         (e = hipMemcpy(d_in, desc->data, sizeof(double) * 6 * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(c->wk.src, 0, sizeof(Source) * B)) != hipSuccess ||
         (e = hipMemset(c->wk.band, 0, sizeof(ModeBand) * B * nm)) != hipSuccess ||
-        (e = hipMemset(c->wk.done, 0, sizeof(int))) != hipSuccess ||
         (e = hipMemcpy(psd_dev, desc->psd, sizeof(double) * 3 * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = launch_setup_data(psd_dev, d_in, c->d, c->w, c->pre, scratch, c->dhi32, c->dlo32, c->sw32, c->g,
                                4.0 * desc->df, nullptr)) != hipSuccess ||

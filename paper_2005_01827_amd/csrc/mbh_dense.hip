@@ -674,19 +674,55 @@ __device__ __forceinline__ void ff_resid_add(float dh, float dl, float ht, float
 // waits than four (measured 6 % faster; one 64-bit value is spilled, reloaded
 // once per item); six would spill 32 values and ran 27 % slower.  The other
 // instantiations keep three or four, where the tighter bound would spill more.
-template <bool kWriteH, bool kF32, int NB, bool kROnly>
-__global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 : 3)) void k_dense(DenseArgs a)
+// kOne: one walker with no item list (launch_dense with walker_one); every
+// workgroup forms the walker's band from its mode bands (an invalid walker
+// has no active mode, so its band is empty) and takes the walker's tiles in
+// order, and workgroup 0 stores the band and the scan over walkers for the
+// reduction.
+// One walker fills at most one workgroup per compute unit, so kOne takes
+// two wavefronts per SIMD and the registers to spill nothing.
+template <bool kWriteH, bool kF32, int NB, bool kROnly, bool kOne = false>
+__global__ __launch_bounds__(kDenseThreads, kOne ? 2 : kROnly ? 5 : ((NB == 1 || kF32) ? 4 : 3)) void k_dense(DenseArgs a)
 {
     static_assert(!kROnly || !kWriteH, "residual-only sums only on the likelihood paths");
+    static_assert(!kOne || kROnly, "one-walker launches only on the likelihood paths");
     __shared__ double red[kDenseThreads / 64][kPartials];
     __shared__ double2 rot[kRotN];
     __shared__ int xcur[kDenseThreads / 64][kMaxModes];   // interval of a deferred mode, per wavefront
-    const int total = min(a.wbase[a.B], a.max_items);
+    __shared__ WalkerBand one;                            // kOne: the walker's band
+    int total = kOne ? 0 : min(a.wbase[a.B], a.max_items);
+    if (kOne && threadIdx.x == 0) {
+        WalkerBand r;
+        r.klo = 0;
+        r.khi = -1;
+        r.tile_lo = 0;
+        r.ntiles = 0;
+        int lo = 0x7fffffff, hi = -1;
+        for (int m = 0; m < a.nm; ++m) {
+            const ModeBand mb = a.band[m];
+            if (!mb.active) continue;
+            lo = min(lo, mb.klo);
+            hi = max(hi, mb.khi);
+        }
+        if (hi >= lo) {
+            r.klo = lo;
+            r.khi = hi;
+            r.tile_lo = (lo - a.k0) / a.tile_bins;
+            r.ntiles = (hi - a.k0) / a.tile_bins - r.tile_lo + 1;
+        }
+        one = r;
+        if (blockIdx.x == 0) {
+            const_cast<WalkerBand *>(a.wband)[0] = r;
+            const_cast<int *>(a.wbase)[0] = 0;
+            const_cast<int *>(a.wbase)[1] = r.ntiles;
+        }
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ns = a.ns;
     CisConst K;
     load_cis(K, a.cis_tab, rot);
     __syncthreads();
+    if (kOne) total = min(uni_i(one.ntiles), a.max_items);
     CisConst32 Kf;
     if (kF32) load_cis32(Kf, a.cis32);
     // Items: a fixed stride over the tile-major list, the items of one walker
@@ -715,13 +751,13 @@ __global__ __launch_bounds__(kDenseThreads, kROnly ? 5 : ((NB == 1 || kF32) ? 4 
         if (tickets && threadIdx.x == 0) next_item[par ^ 1] = (int)gridDim.x + atomicAdd(a.ticket, 1);
         // item values are wave-uniform: held in scalar registers, so that
         // none occupies a vector register across the item
-        const int wk = a.one_per_walker ? (int)blockIdx.x : uni_i(a.item_w[item]);
-        WalkerBand wb = a.wband[wk];
+        const int wk = a.one_per_walker ? (int)blockIdx.x : kOne ? 0 : uni_i(a.item_w[item]);
+        WalkerBand wb = kOne ? one : a.wband[wk];
         wb.klo = uni_i(wb.klo);
         wb.khi = uni_i(wb.khi);
         wb.tile_lo = uni_i(wb.tile_lo);
-        const int base = uni_i(a.wbase[wk]);
-        const int tile = a.one_per_walker ? wb.tile_lo + (item - base) : uni_i(a.item_t[item]);
+        const int base = kOne ? 0 : uni_i(a.wbase[wk]);
+        const int tile = a.one_per_walker || kOne ? wb.tile_lo + (item - base) : uni_i(a.item_t[item]);
         const int slot = uni_i(base + (tile - wb.tile_lo));
         const int kw = uni_i(a.k0 + tile * a.tile_bins + wave * (64 * a.steps));
         const int kwl = kw + 64 * a.steps - 1;
@@ -1167,7 +1203,7 @@ hipError_t launch_setup_data(const double *psd, const double2 *d_in, double2 *d,
 hipError_t launch_walker_bands(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st)
 {
     // a single walker's band is built with its items (launch_items), which
-    // every dense launch runs first
+    // a dense launch runs first, or by the dense kernel itself (walker_one)
     if (B <= 1) return hipSuccess;
     k_walker_bands<<<(B + 127) / 128, 128, 0, st>>>(B, md.nm, g, wk.src, wk.band, wk.wband);
     k_scan_walkers<<<1, 1024, 0, st>>>(B, wk.wband, wk.wbase);
@@ -1189,17 +1225,22 @@ void launch_items(int B, int nm, const GridDesc &g, const Work &wk, int max_item
 
 hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &wk, const Data &dt, int max_items,
                         const Schedule &sch, bool inner, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
-                        bool items_ready)
+                        bool walker_one)
 {
     if (B <= 0) return hipSuccess;
-    if (!items_ready) launch_items(B, md.nm, g, wk, max_items, st);
+    walker_one = walker_one && B == 1 && !sch.one_per_walker && !inner;
+    if (!walker_one) launch_items(B, md.nm, g, wk, max_items, st);
     DenseArgs a = make_args(B, md, g, wk, dt, max_items);
     a.one_per_walker = sch.one_per_walker;
     a.use_ticket = sch.one_per_walker ? 0 : 1;
     const int grid = dense_grid(B, g, sch);
     hipError_t e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
-    if (g.precision != 0 && inner)
+    if (walker_one && g.precision != 0)
+        k_dense<false, true, kBinsPerLane, true, true><<<grid, kDenseThreads, 0, st>>>(a);
+    else if (walker_one)
+        k_dense<false, false, kBinsPerLane, true, true><<<grid, kDenseThreads, 0, st>>>(a);
+    else if (g.precision != 0 && inner)
         k_dense<false, true, kBinsPerLane, false><<<grid, kDenseThreads, 0, st>>>(a);
     else if (g.precision != 0)
         k_dense<false, true, kBinsPerLane, true><<<grid, kDenseThreads, 0, st>>>(a);

@@ -108,20 +108,15 @@ struct Work {
     double *cis_tab;        // constants of the dense-stage sin/cos
     float *cis32;           // the same for the FP32 dense stage
     float *coef32;          // [B][nm][ns-1][32] FP32 copy of coef (FP32 dense stage)
-    int *done;              // mode workgroups of the single walker finished in k_sparse (0 between launches)
 };
 
-// Outputs of the fused sparse kernel (the Work arrays it writes) and, with
-// done set (one walker), the work-item list it builds.
+// Outputs of the fused sparse kernel (the Work arrays it writes).
 struct SparseArgs {
     Source *src;
     ModeBand *band;
     double *kf, *kt, *fn, *coef;
     int *kbin;
-    int *done;
-    WalkerBand *wband;
-    int *wbase, *tile_off, *ticket, *item_w, *item_t;
-    int max_items;
+    int *ticket;            // if not null: zeroed, for a dense launch with walker_one
 };
 
 // Union band of walker w's active modes and its range of tiles.
@@ -224,11 +219,11 @@ hipError_t launch_response(int B, const Modes &md, const GridDesc &g, const Work
 hipError_t launch_spline(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st);
 
 // launch_waveform + launch_response + launch_spline as one kernel, one
-// workgroup per (walker, mode), writing the same bits; with items and
-// B = 1 it also builds the work-item list (launch_walker_bands is then not
-// needed).
+// workgroup per (walker, mode), writing the same bits; with reset_ticket it
+// also zeroes the dense stage's work-item counter, for a launch_dense with
+// walker_one (one walker: no item list to build).
 hipError_t launch_sparse(const double *params, int B, const Modes &md, const GridDesc &g, const Work &wk,
-                         int max_items, bool items, hipStream_t st);
+                         bool reset_ticket, hipStream_t st);
 
 // Batches up to this size take the fused sparse kernel on the graph path.
 constexpr int kFusedSparseMaxBatch = 1;
@@ -249,11 +244,15 @@ int num_cus();
 // ev0/ev1 (optional) are recorded on st right before and after the dense
 // kernel.  inner = false: the FP64 path accumulates only the residual sums
 // (enough for ln L); <d|h>_c and <h|h>_c of the output are then zero.
-// items_ready: the work-item list is already built (launch_sparse with one
-// walker); otherwise the launch builds it first.
+// walker_one (B = 1, the item counter already zero, as launch_sparse with
+// reset_ticket leaves it; not with one_per_walker): no item list is built;
+// every workgroup forms the walker's band from its mode bands and takes the
+// walker's tiles in order from the counter, and workgroup 0 stores the band
+// and the scan over walkers for the reduction.  Otherwise the launch builds
+// the work-item list first.
 hipError_t launch_dense(int B, const Modes &md, const GridDesc &g, const Work &wk, const Data &dt,
                         int max_items, const Schedule &sch, bool inner, hipStream_t st, hipEvent_t ev0 = nullptr,
-                        hipEvent_t ev1 = nullptr, bool items_ready = false);
+                        hipEvent_t ev1 = nullptr, bool walker_one = false);
 
 hipError_t launch_reduce(int B, const GridDesc &g, const Work &wk, const Data &dt, double *out7,
                          double *logL, hipStream_t st);

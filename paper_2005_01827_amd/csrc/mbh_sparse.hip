@@ -980,12 +980,11 @@ __global__ __launch_bounds__(kSplineThreads) void k_spline(int B, Modes md, Grid
 
 // ---------------------------------------------------------------------------
 // The whole sparse stage of one (walker, mode) in one workgroup: the
-// walker's constants (each of its mode workgroups computes them, lane group
-// 0 of wavefront 0), the mode's band (the same group), its knots and the
-// response there (one thread per knot, with no round trip through memory
-// between the two) and the spline.  With a.done set (one walker), the last
-// of the walker's mode workgroups to have its band also builds the work-item
-// list, as k_items_one does; the counter is reset for the next launch.
+// walker's constants (each of its mode workgroups computes them, wavefront
+// 0) and the mode's weights (wavefront 1) at once, the mode's band
+// (wavefront 0), its knots and the response there (one thread per knot, with
+// no round trip through memory between the two) and the spline.  With
+// a.ticket set, workgroup 0 also zeroes the dense stage's item counter.
 // ---------------------------------------------------------------------------
 template <int G>
 __global__ __launch_bounds__(kSplineThreads) void k_sparse(const double *__restrict__ params, int B, Modes md,
@@ -995,7 +994,6 @@ __global__ __launch_bounds__(kSplineThreads) void k_sparse(const double *__restr
     __shared__ Source ss;
     __shared__ ModeBand sb;
     __shared__ double swt[4];                      // the mode's K+ and Kx
-    __shared__ int last;
     const int wm = blockIdx.x;
     if (wm >= B * md.nm) return;                   // whole workgroups leave together
     const int w = wm / md.nm, im = wm - w * md.nm;
@@ -1033,23 +1031,7 @@ __global__ __launch_bounds__(kSplineThreads) void k_sparse(const double *__restr
         }
     }
     __syncthreads();
-    if (a.done) {
-        // one walker: the last of its mode workgroups to have its band builds
-        // the work-item list, while the others go on with their knots
-        // (thread 0 wrote this workgroup's band and source, and it alone
-        // reads the other modes' bands in items_one, so it alone fences)
-        if (threadIdx.x == 0) {
-            __threadfence();                       // this workgroup's band and source before the count
-            last = atomicAdd(a.done, 1) == md.nm - 1;
-            if (last) __threadfence();             // every mode's band after the count
-        }
-        __syncthreads();
-        if (last) {
-            items_one(md.nm, g, a.src, a.band, a.wband, a.wbase, a.tile_off, a.ticket, a.item_w, a.item_t,
-                      a.max_items);
-            if (threadIdx.x == 0) *a.done = 0;
-        }
-    }
+    if (a.ticket && wm == 0 && threadIdx.x == 0) *a.ticket = 0;
     // the knots read the walker's constants and the band from LDS as needed
     const ModeBand &b = sb;
     double *fnm = a.fn + (size_t)wm * kNumFn * ns;
@@ -1132,7 +1114,7 @@ hipError_t launch_spline(int B, const Modes &md, const GridDesc &g, const Work &
 }
 
 hipError_t launch_sparse(const double *params, int B, const Modes &md, const GridDesc &g, const Work &wk,
-                         int max_items, bool items, hipStream_t st)
+                         bool reset_ticket, hipStream_t st)
 {
     if (B <= 0) return hipSuccess;
     SparseArgs a;
@@ -1143,14 +1125,7 @@ hipError_t launch_sparse(const double *params, int B, const Modes &md, const Gri
     a.fn = wk.fn;
     a.coef = wk.coef;
     a.kbin = wk.kbin;
-    a.done = (items && B == 1) ? wk.done : nullptr;
-    a.wband = wk.wband;
-    a.wbase = wk.wbase;
-    a.tile_off = wk.tile_off;
-    a.ticket = wk.ticket;
-    a.item_w = wk.item_w;
-    a.item_t = wk.item_t;
-    a.max_items = max_items;
+    a.ticket = reset_ticket ? wk.ticket : nullptr;
     const size_t lds = spline_lds_bytes(g.ns);
     const unsigned grid = (unsigned)(B * md.nm);
     switch (spline_group(g.ns)) {
