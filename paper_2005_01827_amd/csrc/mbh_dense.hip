@@ -1045,9 +1045,23 @@ __global__ void k_reduce(int B, GridDesc g, const Source *__restrict__ src, cons
     }
     double acc[kPartials];
     for (int q = 0; q < kPartials; ++q) acc[q] = 0.0;
+    // each lane adds its items in increasing order; the partials of four
+    // of them are loaded (at clamped indices) before any is added
     const int b0 = wbase[w], b1 = wbase[w + 1];
-    for (int it = b0 + lane; it < b1; it += 64)
-        for (int q = 0; q < kPartials; ++q) acc[q] += partial[(size_t)it * kPartials + q];
+    for (int it0 = b0; it0 < b1; it0 += 4 * 64) {
+        double v[4][kPartials];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const size_t it = (size_t)min(it0 + lane + 64 * u, b1 - 1);
+#pragma unroll
+            for (int q = 0; q < kPartials; ++q) v[u][q] = partial[it * kPartials + q];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (it0 + lane + 64 * u < b1)
+#pragma unroll
+                for (int q = 0; q < kPartials; ++q) acc[q] += v[u][q];
+    }
     for (int q = 0; q < kPartials; ++q) {
         double v = acc[q];
         for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
