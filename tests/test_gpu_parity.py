@@ -68,6 +68,81 @@ def test_sparse_stage_matches_oracle(small, oracle):
         assert err.max() < 1e-10, (i, err.max())
 
 
+def _compare_sparse(g, o, tag):
+    """Band edges exactly; knots to 1e-14; amplitude and phase to 1e-11 of
+    their own largest value over the mode; the six response functions (Re
+    and Im of T^A, T^E, T^T) to 1e-11 of the mode's response scale, the
+    largest of the six.  At low frequency T^T = (X + Y + Z) / sqrt(3) is a
+    near-cancellation of terms of that scale (Sec. II, the A/E/T
+    combinations), so its rounding is measured against them: relative to its
+    own small values it can differ from the oracle by 1e-7 with both sides
+    correct to rounding."""
+    assert np.array_equal(g["band"], o["band"]), (tag, g["band"], o["band"])
+    assert np.allclose(g["fband"], o["fband"], rtol=1e-14, atol=0), tag
+    assert np.allclose(g["f"], o["f"], rtol=1e-14, atol=0), tag
+    resp = np.abs(o["fn"][:, 2:8]).max(axis=(1, 2))[:, None] + 1e-300
+    for q in range(8):
+        scale = np.abs(o["fn"][:, q]).max(axis=1, keepdims=True) + 1e-300 if q < 2 else resp
+        err = np.abs(g["fn"][:, q] - o["fn"][:, q]) / scale
+        assert err.max() < 1e-11, (tag, q, err.max())
+
+
+def test_band_edges_over_wide_mass_and_time_ranges(oracle):
+    """The wavefront root searches (f_peak, each mode's f_start) against the
+    oracle's halving, band edges bit for bit, over 96 walkers from 1e4 to
+    3e8 solar masses and coalescence times from before the observation to
+    after it, so that every outcome of the f_start search occurs: a mode
+    already in band at the grid's first frequency, a start inside the band,
+    and no band.  The batch takes the staged kernels; every fourth walker
+    also goes through the fused one-walker kernel."""
+    from paper_2005_01827_amd import mbh
+    w = inputs.small_config(1, seed=7)
+    g = w.grid
+    T = 2.0 ** 20
+    rng = np.random.default_rng(2024)
+    n = 96
+    th = np.empty((n, 11))
+    th[:, 0] = np.exp(rng.uniform(math.log(1e4), math.log(3e8), n))
+    th[:, 1] = rng.uniform(0.1, 1.0, n)
+    th[:, 2:4] = rng.uniform(-0.9, 0.9, (n, 2))
+    th[:, 4] = rng.uniform(1.0, 50.0, n)
+    th[:, 5] = rng.uniform(0.0, 2 * math.pi, n)
+    th[:, 6] = rng.uniform(0.05, math.pi - 0.05, n)
+    th[:, 7] = rng.uniform(0.0, 2 * math.pi, n)
+    th[:, 8] = rng.uniform(-1.5, 1.5, n)
+    th[:, 9] = rng.uniform(0.0, math.pi, n)
+    th[:, 10] = rng.uniform(-0.1 * T, 0.1 * T, n)
+    th[::8, 10] = -0.95 * T                        # merged before the observation starts
+    print(f"case: band edges, {n} walkers, M_T 1e4..3e8, small grid", flush=True)
+    psd = inputs.psd_aet(g.freqs)
+    d = inputs.noise(g, psd, 5)
+    flo = g.k0 * g.df
+    counts = dict(at_flo=0, inside=0, none=0)
+    L = mbh.Likelihood(g, d, psd, w.modes, w.ns, w.t0, max_batch=n)
+    L1 = mbh.Likelihood(g, d, psd, w.modes, w.ns, w.t0, max_batch=1)
+    try:
+        B = L.waveform_gen(th)
+        L.response(B)
+        for i in range(n):
+            o = oracle.sparse(th[i], g, w.modes, w.ns, w.t0)
+            _compare_sparse(L.get_sparse(i), o, i)
+            for m in range(len(w.modes)):
+                if not o["band"][m, 0]:
+                    counts["none"] += 1
+                elif o["fband"][m, 0] == flo:
+                    counts["at_flo"] += 1
+                else:
+                    counts["inside"] += 1
+            if i % 4 == 0:
+                L1.loglike(th[i:i + 1])
+                _compare_sparse(L1.get_sparse(0), o, ("fused", i))
+    finally:
+        L.close()
+        L1.close()
+    print(f"[band edges] mode outcomes {counts}", flush=True)
+    assert min(counts.values()) >= 20, counts
+
+
 def test_dense_stage_on_oracle_sparse_functions(small, oracle):
     """Dense interpolation + inner products fed the oracle's own knots and
     knot values: isolates the dense kernel and the device spline setup."""
