@@ -225,8 +225,10 @@ hipError_t launch_spline(int B, const Modes &md, const GridDesc &g, const Work &
 hipError_t launch_sparse(const double *params, int B, const Modes &md, const GridDesc &g, const Work &wk,
                          bool reset_ticket, hipStream_t st);
 
-// Batches up to this size take the fused sparse kernel on the graph path.
-constexpr int kFusedSparseMaxBatch = 1;
+// Batches up to this size take the fused sparse kernel on the graph path
+// (measured on the 2^22-s grid: 8-10 % less time per call than the chain of
+// five kernels from 2 to 32 walkers, 6 % more at 64).
+constexpr int kFusedSparseMaxBatch = 32;
 
 hipError_t launch_walker_bands(int B, const Modes &md, const GridDesc &g, const Work &wk, hipStream_t st);
 

@@ -266,11 +266,12 @@ def test_mode_subsets_and_knot_counts(oracle, modes, ns):
 
 @pytest.mark.parametrize("ns", [8, 300, 560, 769, 1024])
 def test_single_walker_fused_sparse_matches_batch(oracle, ns):
-    """One walker takes the fused sparse kernel (the whole sparse stage and
-    its item list in one launch); a batch takes one kernel per step.  Knot
-    counts chosen so the spline solves 8, 4, 2 and 1 functions per pass and
-    leaves 1 to 64 interleaved systems to the Thomas sweeps: each walker
-    alone gives bitwise its batched ln L, which matches the oracle."""
+    """Small batches take the fused sparse kernel (the whole sparse stage in
+    one launch; one walker also the dense kernel without an item list); the
+    staged entry points take one kernel per step.  Knot counts chosen so the
+    spline solves 8, 4, 2 and 1 functions per pass and leaves 1 to 64
+    interleaved systems to the Thomas sweeps: each walker alone and the
+    three together give bitwise the staged ln L, which matches the oracle."""
     import torch
     from paper_2005_01827_amd import mbh
     print(f"case: one walker against a batch, ns={ns}", flush=True)
@@ -280,7 +281,9 @@ def test_single_walker_fused_sparse_matches_batch(oracle, ns):
     d = oracle.template(w.injection, g, w.modes, ns, w.t0) + inputs.noise(g, psd, 79)
     L = mbh.Likelihood(g, d, psd, w.modes, ns, w.t0, max_batch=4)
     try:
-        batch = L.loglike(w.walkers).cpu().numpy()
+        batch = L.stages(w.walkers).cpu().numpy()[:, 0]
+        fused = L.loglike(w.walkers).cpu().numpy()
+        assert np.array_equal(fused, batch), (ns, fused, batch)
         for i in range(len(w.walkers)):
             one = L.loglike(w.walkers[i:i + 1]).cpu().numpy()
             assert np.array_equal(one, batch[i:i + 1]), (ns, i, one, batch[i])
