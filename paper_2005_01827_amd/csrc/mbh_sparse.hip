@@ -43,6 +43,7 @@
 // Spline setup (Sec. II.A): not-a-knot cubic splines of the eight real
 // functions of each mode (A, phi, Re/Im T^A, T^E, T^T) over the log-spaced
 // knots, by parallel cyclic reduction of the second-derivative system.
+#include <type_traits>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -697,7 +698,7 @@ __device__ __forceinline__ int first_bin(double x, double df)
 
 constexpr int kSplineThreads = 256;
 constexpr int kThomasRows = 16;    // rows per interleaved system left for the Thomas sweeps
-constexpr int kSplineRows = 4;     // rows per thread: ns - 2 <= 1024
+constexpr int kSplineRows = 4;     // most rows per thread: ns - 2 <= 1024
 constexpr int kCoefChunk = 8;      // coefficient items per thread whose loads are issued together
 
 // LDS of one spline workgroup solving G functions together: the matrix
@@ -721,6 +722,14 @@ __host__ __device__ inline int spline_group(int ns)
     return G;
 }
 inline size_t spline_lds_bytes(int ns) { return spline_lds_for(ns, spline_group(ns)); }
+// Rows per thread of the cyclic reduction (1, 2 or kSplineRows): only as
+// many as the ns - 2 rows need, since the rows of a round are held in
+// registers across its barrier.
+__host__ __device__ inline int spline_rows(int ns)
+{
+    const int m = ns - 2;
+    return m <= kSplineThreads ? 1 : m <= 2 * kSplineThreads ? 2 : kSplineRows;
+}
 
 // Not-a-knot splines through (f_j, y_j) of (walker, mode) wm, by one workgroup
 // of kSplineThreads threads with sm its dynamic LDS (spline_lds_for(ns, G)).
@@ -737,7 +746,7 @@ inline size_t spline_lds_bytes(int ns) { return spline_lds_for(ns, spline_group(
 // the cubic of interval i re-centred on fc = kbin[i+1] df, the first dense
 // bin of the next interval: q(t) = p(t + fc - f_i), evaluated by the dense
 // stage at t = f - fc.
-template <int G>
+template <int G, int R>
 __device__ __forceinline__ void spline_solve(int wm, const GridDesc &g, bool act, const double *__restrict__ kf,
                                              const double *__restrict__ fn, double *__restrict__ coef,
                                              int *__restrict__ kbin, double *sm)
@@ -803,9 +812,9 @@ __device__ __forceinline__ void spline_solve(int wm, const GridDesc &g, bool act
         int P = 1;
         while (P * kThomasRows < m) P *= 2;
         for (int s = 1; s < P; s *= 2) {
-            double na[kSplineRows], nb[kSplineRows], nc[kSplineRows], nd[kSplineRows][G];
+            double na[R], nb[R], nc[R], nd[R][G];
 #pragma unroll
-            for (int u = 0; u < kSplineRows; ++u) {
+            for (int u = 0; u < R; ++u) {
                 if (u * kSplineThreads < m) {
                     // neighbour indices clamped into the system, so that every
                     // load of the round is issued at once, with no branch; a
@@ -835,7 +844,7 @@ __device__ __forceinline__ void spline_solve(int wm, const GridDesc &g, bool act
             }
             __syncthreads();
 #pragma unroll
-            for (int u = 0; u < kSplineRows; ++u) {
+            for (int u = 0; u < R; ++u) {
                 const int r = threadIdx.x + u * kSplineThreads;
                 if (r < m) {
                     A[r] = na[u];
@@ -965,7 +974,7 @@ __device__ __forceinline__ void spline_solve(int wm, const GridDesc &g, bool act
 }
 
 // Kernel 5: one workgroup per (walker, mode).
-template <int G>
+template <int G, int R>
 __global__ __launch_bounds__(kSplineThreads) void k_spline(int B, Modes md, GridDesc g,
                                                            const ModeBand *__restrict__ band,
                                                            const double *__restrict__ kf,
@@ -975,7 +984,7 @@ __global__ __launch_bounds__(kSplineThreads) void k_spline(int B, Modes md, Grid
     extern __shared__ double sm[];
     const int wm = blockIdx.x;
     if (wm >= B * md.nm) return;
-    spline_solve<G>(wm, g, band[wm].active != 0, kf, fn, coef, kbin, sm);
+    spline_solve<G, R>(wm, g, band[wm].active != 0, kf, fn, coef, kbin, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -986,7 +995,7 @@ __global__ __launch_bounds__(kSplineThreads) void k_spline(int B, Modes md, Grid
 // no round trip through memory between the two) and the spline.  With
 // a.ticket set, workgroup 0 also zeroes the dense stage's item counter.
 // ---------------------------------------------------------------------------
-template <int G>
+template <int G, int R>
 __global__ __launch_bounds__(kSplineThreads) void k_sparse(const double *__restrict__ params, int B, Modes md,
                                                            GridDesc g, SparseArgs a)
 {
@@ -1052,21 +1061,41 @@ __global__ __launch_bounds__(kSplineThreads) void k_sparse(const double *__restr
         for (int q = 0; q < 7; ++q) fnm[(q + 1) * ns + j] = r[q];
     }
     __syncthreads();
-    spline_solve<G>(wm, g, b.active != 0, a.kf, a.fn, a.coef, a.kbin, sm);
+    spline_solve<G, R>(wm, g, b.active != 0, a.kf, a.fn, a.coef, a.kbin, sm);
 }
 
 }  // namespace
 
 const void *source_kernel() { return reinterpret_cast<const void *>(&k_source); }
 
+// f(G, R) with G and R as compile-time constants, for the shapes the knot
+// counts can take: all eight functions together whenever they fit (up to
+// about 540 knots, so up to 4 rows per thread), fewer only with more than
+// 512 rows (4 rows per thread).  Returns false for any other pair.
+template <typename F>
+bool with_spline_shape(int ns, F f)
+{
+    const int G = spline_group(ns), R = spline_rows(ns);
+    using std::integral_constant;
+    if (G == kNumFn && R == 1) return f(integral_constant<int, kNumFn>(), integral_constant<int, 1>()), true;
+    if (G == kNumFn && R == 2) return f(integral_constant<int, kNumFn>(), integral_constant<int, 2>()), true;
+    if (G == kNumFn && R == kSplineRows)
+        return f(integral_constant<int, kNumFn>(), integral_constant<int, kSplineRows>()), true;
+    if (G == kNumFn / 2 && R == kSplineRows)
+        return f(integral_constant<int, kNumFn / 2>(), integral_constant<int, kSplineRows>()), true;
+    if (G == kNumFn / 4 && R == kSplineRows)
+        return f(integral_constant<int, kNumFn / 4>(), integral_constant<int, kSplineRows>()), true;
+    if (G == 1 && R == kSplineRows) return f(integral_constant<int, 1>(), integral_constant<int, kSplineRows>()), true;
+    return false;
+}
+
 const void *sparse_kernel(int ns)
 {
-    switch (spline_group(ns)) {
-    case kNumFn: return reinterpret_cast<const void *>(&k_sparse<kNumFn>);
-    case kNumFn / 2: return reinterpret_cast<const void *>(&k_sparse<kNumFn / 2>);
-    case kNumFn / 4: return reinterpret_cast<const void *>(&k_sparse<kNumFn / 4>);
-    default: return reinterpret_cast<const void *>(&k_sparse<1>);
-    }
+    const void *k = nullptr;
+    with_spline_shape(ns, [&](auto gc, auto rc) {
+        k = reinterpret_cast<const void *>(&k_sparse<decltype(gc)::value, decltype(rc)::value>);
+    });
+    return k;
 }
 
 hipError_t launch_waveform(const double *params, int B, const Modes &md, const GridDesc &g, const Work &wk,
@@ -1096,20 +1125,11 @@ hipError_t launch_spline(int B, const Modes &md, const GridDesc &g, const Work &
     if (B <= 0) return hipSuccess;
     const size_t lds = spline_lds_bytes(g.ns);
     const unsigned grid = (unsigned)(B * md.nm);
-    switch (spline_group(g.ns)) {
-    case kNumFn:
-        k_spline<kNumFn><<<grid, kSplineThreads, lds, st>>>(B, md, g, wk.band, wk.kf, wk.fn, wk.coef, wk.kbin);
-        break;
-    case kNumFn / 2:
-        k_spline<kNumFn / 2><<<grid, kSplineThreads, lds, st>>>(B, md, g, wk.band, wk.kf, wk.fn, wk.coef, wk.kbin);
-        break;
-    case kNumFn / 4:
-        k_spline<kNumFn / 4><<<grid, kSplineThreads, lds, st>>>(B, md, g, wk.band, wk.kf, wk.fn, wk.coef, wk.kbin);
-        break;
-    default:
-        k_spline<1><<<grid, kSplineThreads, lds, st>>>(B, md, g, wk.band, wk.kf, wk.fn, wk.coef, wk.kbin);
-        break;
-    }
+    if (!with_spline_shape(g.ns, [&](auto gc, auto rc) {
+            k_spline<decltype(gc)::value, decltype(rc)::value>
+                <<<grid, kSplineThreads, lds, st>>>(B, md, g, wk.band, wk.kf, wk.fn, wk.coef, wk.kbin);
+        }))
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -1128,12 +1148,10 @@ hipError_t launch_sparse(const double *params, int B, const Modes &md, const Gri
     a.ticket = reset_ticket ? wk.ticket : nullptr;
     const size_t lds = spline_lds_bytes(g.ns);
     const unsigned grid = (unsigned)(B * md.nm);
-    switch (spline_group(g.ns)) {
-    case kNumFn: k_sparse<kNumFn><<<grid, kSplineThreads, lds, st>>>(params, B, md, g, a); break;
-    case kNumFn / 2: k_sparse<kNumFn / 2><<<grid, kSplineThreads, lds, st>>>(params, B, md, g, a); break;
-    case kNumFn / 4: k_sparse<kNumFn / 4><<<grid, kSplineThreads, lds, st>>>(params, B, md, g, a); break;
-    default: k_sparse<1><<<grid, kSplineThreads, lds, st>>>(params, B, md, g, a); break;
-    }
+    if (!with_spline_shape(g.ns, [&](auto gc, auto rc) {
+            k_sparse<decltype(gc)::value, decltype(rc)::value><<<grid, kSplineThreads, lds, st>>>(params, B, md, g, a);
+        }))
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
