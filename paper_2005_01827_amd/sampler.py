@@ -811,6 +811,11 @@ def ess_comparison(loglike: Callable, logprior: Callable, x0: np.ndarray, betas,
     e1, e2 = max(out["stretch"]["ess"], 1.0), max(out["stretch_flow"]["ess"], 1.0)
     se = np.sqrt(a1.var(0) / e1 + a2.var(0) / e2)
     se_bm = np.sqrt(batch_means_se(ch_plain) ** 2 + batch_means_se(ch_flow) ** 2)
+    # each arm's standard error of the ensemble mean: the larger of its
+    # batch means and its autocorrelation estimate (batches a few ensemble
+    # autocorrelation times long bias the batch means low)
+    se_hi = np.sqrt(np.maximum(batch_means_se(ch_plain), ensemble_mean_se(ch_plain)) ** 2 +
+                    np.maximum(batch_means_se(ch_flow), ensemble_mean_se(ch_flow)) ** 2)
     h = len(ch_plain) // 2
     se_drift = np.sqrt(batch_means_se(ch_plain[:h], 10) ** 2 + batch_means_se(ch_plain[h:], 10) ** 2)
     hf = len(ch_flow) // 2
@@ -818,21 +823,25 @@ def ess_comparison(loglike: Callable, logprior: Callable, x0: np.ndarray, betas,
     with np.errstate(divide="ignore", invalid="ignore"):
         z = np.abs(a1.mean(0) - a2.mean(0)) / se
         z_bm = np.abs(a1.mean(0) - a2.mean(0)) / se_bm
+        z_hi = np.abs(a1.mean(0) - a2.mean(0)) / se_hi
         z_drift = np.abs(ch_plain[:h].reshape(-1, dim).mean(0) - ch_plain[h:].reshape(-1, dim).mean(0)) / se_drift
         z_drift_f = np.abs(ch_flow[:hf].reshape(-1, dim).mean(0) - ch_flow[hf:].reshape(-1, dim).mean(0)) / se_drift_f
         zmax = float(np.nanmax(z))
         sd_rel = float(np.nanmax(np.abs(a2.std(0) / a1.std(0) - 1)))
     zmax_bm = float(np.nanmax(z_bm))
-    # equal accuracy is judged on batch-means standard errors: the
-    # walker-averaged estimate misses correlation between walkers and
-    # understates the error of an ensemble's mean
+    zmax_hi = float(np.nanmax(z_hi))
+    # equal accuracy is judged on standard errors of the ensemble mean (the
+    # larger of batch means and autocorrelation): the walker-averaged
+    # estimate misses correlation between walkers and understates the error
+    # of an ensemble's mean
     out["accuracy"] = {"max_mean_diff_in_se": round(zmax, 3), "max_sd_rel_diff": round(sd_rel, 4),
                        # the comparison needs runs longer than 50 times the
                        # integrated time, here that of the ensemble mean
                        "runs_over_50_ensemble_tau": bool(out["stretch"]["chain_over_50_ensemble_tau"] and
                                                          out["stretch_flow"]["chain_over_50_ensemble_tau"]),
                        "max_mean_diff_in_batch_means_se": round(zmax_bm, 3),
-                       "equal": bool(zmax_bm < 3 and sd_rel < 0.05),
+                       "max_mean_diff_in_ensemble_se": round(zmax_hi, 3),
+                       "equal": bool(zmax_hi < 3 and sd_rel < 0.05),
                        "mean_diff_in_se": [round(float(v), 2) for v in z],
                        "mean_diff_in_batch_means_se": [round(float(v), 2) for v in z_bm],
                        "stretch_arm_half_vs_half_in_batch_means_se": [round(float(v), 2) for v in z_drift],
