@@ -759,12 +759,13 @@ def ess_comparison(loglike: Callable, logprior: Callable, x0: np.ndarray, betas,
     'seconds', the flow arm's training included.  ESS (Sec. III.C) counts
     the arm's T = 1 chain; ESS/s divides by the arm's wall time.  Accuracy:
     per-parameter means of the two arms agree within 3 combined Monte Carlo
-    standard errors (batch means of the ensemble mean), and standard
-    deviations within 5 %.  Also reported: the
-    mean differences in batch-means standard errors (which see correlation
-    between walkers) and the stretch arm's first half against its second half
-    (a drift check).  keep_chains adds both arms' T = 1 chains to the result
-    under 'chains'.
+    standard errors of the ensemble means (each arm's the larger of its
+    batch means and its autocorrelation estimate), and standard deviations
+    within 5 %.  Also reported: the mean differences in walker-averaged and
+    in batch-means standard errors (the latter see correlation between
+    walkers) and each arm's first half against its second half (a drift
+    check).  keep_chains adds both arms' T = 1 chains to the result under
+    'chains'.
     """
     say = log or (lambda *_: None)
     dim = x0.shape[-1]
