@@ -88,9 +88,13 @@ def test_fp32c_small_grid_error_model(oracle, snr):
     try:
         out = L.stages(walkers).cpu().numpy()
         lnl = L.loglike(walkers).cpu().numpy()
+        # one walker alone (fused sparse kernel, the one-walker dense
+        # kernel) gives its batched value bit for bit
+        ones = np.array([L.loglike(walkers[i:i + 1]).cpu().numpy()[0] for i in (0, 6, 11)])
         torch.cuda.synchronize()
     finally:
         L.close()
+    assert np.array_equal(ones, lnl[[0, 6, 11]]), (ones, lnl[[0, 6, 11]])
     ref = oracle.loglike(walkers, g, d, psd, w.modes, w.ns, w.t0)
     sig = model_sigma(oracle, walkers, g, d, psd, w.modes, w.ns, w.t0)
     err = np.abs(out[:, 0] - ref[:, 0])
