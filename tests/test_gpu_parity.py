@@ -295,6 +295,31 @@ def test_single_walker_fused_sparse_matches_batch(oracle, ns):
         L.close()
 
 
+def test_fused_threshold_bitwise(oracle):
+    """Batches of up to 32 walkers take the fused sparse kernel, larger ones
+    the chain of five kernels: the same walkers give the same bits either
+    way (32 fused against 33 and 40 through the chain), and one of them
+    matches the oracle."""
+    import torch
+    from paper_2005_01827_amd import mbh
+    print("case: fused sparse threshold, 32 / 33 / 40 walkers", flush=True)
+    w = inputs.small_config(40, seed=17)
+    g = w.grid
+    psd = inputs.psd_aet(g.freqs)
+    d = oracle.template(w.injection, g, w.modes, w.ns, w.t0) + inputs.noise(g, psd, 81)
+    L = mbh.Likelihood(g, d, psd, w.modes, w.ns, w.t0, max_batch=40)
+    try:
+        a = L.loglike(w.walkers[:32]).cpu().numpy()
+        b = L.loglike(w.walkers[:33]).cpu().numpy()
+        c = L.loglike(w.walkers).cpu().numpy()
+        torch.cuda.synchronize()
+    finally:
+        L.close()
+    assert np.array_equal(a, b[:32]) and np.array_equal(b, c[:33]), (a - b[:32], b - c[:33])
+    ref = oracle.loglike(w.walkers[:2], g, d, psd, w.modes, w.ns, w.t0)
+    assert np.all(_lnl_close(a[:2], ref[:, 0]))
+
+
 def test_noiseless_injection_from_gpu_template_is_zero(small):
     import torch
     from paper_2005_01827_amd import mbh
