@@ -217,20 +217,25 @@ __device__ __forceinline__ double lane_value(double v, int j)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-template <typename F>
-__device__ void wave_root(double &lo, double &hi, double &glo, double &ghi, F g)
+// The point of lane 'lane' in wave_root's first round over [lo, hi].
+__device__ __forceinline__ double wave_root_point(double lo, double hi, int lane)
+{
+    const bool wide = lo > 0.0 && hi > 2.0 * lo;
+    const double L = wide ? log(hi / lo) : 0.0;
+    const double t = (double)lane * (1.0 / 63.0);
+    return lane == 0 ? lo : lane == 63 ? hi : wide ? lo * exp(L * t) : fma(hi - lo, t, lo);
+}
+
+// g0 serves the first round (it may return values formed ahead of time for
+// the points of wave_root_point), g every later one.
+template <typename F, typename F0>
+__device__ void wave_root(double &lo, double &hi, double &glo, double &ghi, F g, F0 g0)
 {
     typedef unsigned long long lanes_t;
     const int lane = threadIdx.x & 63;
-    double x, v = 0.0, d = 0.0;
-    {
-        const bool wide = lo > 0.0 && hi > 2.0 * lo;
-        const double L = wide ? log(hi / lo) : 0.0;
-        const double t = (double)lane * (1.0 / 63.0);
-        x = lane == 0 ? lo : lane == 63 ? hi : wide ? lo * exp(L * t) : fma(hi - lo, t, lo);
-    }
+    double x = wave_root_point(lo, hi, lane), v = 0.0, d = 0.0;
     const bool in0 = lane == 0 || lane == 63 || (x > lo && x < hi);
-    if (in0) g(x, v, d);
+    if (in0) g0(x, v, d);
     glo = lane_value(v, 0);
     ghi = lane_value(v, 63);
     if (!(glo < 0.0 && ghi >= 0.0)) return;
@@ -310,12 +315,17 @@ __device__ void wave_root(double &lo, double &hi, double &glo, double &ghi, F g)
     }
 }
 
+template <typename F>
+__device__ void wave_root(double &lo, double &hi, double &glo, double &ghi, F g)
+{
+    wave_root(lo, hi, glo, ghi, g, g);
+}
+
 // ---------------------------------------------------------------------------
-// Per-walker constants (a1 and the alignment at f_peak), from the 11
-// parameters at p.  Called by a whole wavefront, whose lanes share
-// the root search for f_peak; every lane returns the same value.
+// Per-walker constants (a1) from the 11 parameters at p, all but f_peak and
+// the alignment there (source_of adds those).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ Source source_of(const double *__restrict__ p, double t0)
+__device__ __forceinline__ Source source_consts(const double *__restrict__ p, double t0)
 {
     Source s;
     for (int i = 0; i < (int)(sizeof(Source) / sizeof(double)); ++i) reinterpret_cast<double *>(&s)[i] = 0.0;
@@ -384,7 +394,19 @@ __device__ __forceinline__ Source source_of(const double *__restrict__ p, double
     s.cR = -0.375 * pow(s.fJ, 11.0 / 3.0) * (d2j + s.kRD / (s.fd * (1.0 + uj * uj)));
     s.b1 = d1j - s.cR * pow(s.fJ, -8.0 / 3.0) + s.kRD * atan(uj);
     s.b0 = pj - s.b1 * s.fJ + 0.6 * s.cR * pow(s.fJ, -5.0 / 3.0) + s.kRD * s.fd * (uj * atan(uj) - 0.5 * log1p(uj * uj));
+    return s;
+}
 
+// ---------------------------------------------------------------------------
+// Per-walker constants (a1 and the alignment at f_peak), from the 11
+// parameters at p.  Called by a whole wavefront, whose lanes share
+// the root search for f_peak; every lane returns the same value.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ Source source_of(const double *__restrict__ p, double t0)
+{
+    Source s = source_consts(p, t0);
+    if (!s.valid) return s;
+    const double eta = s.eta;
     // f_peak: root of d ln(f^2 A_22)/df on [f_J, f_RD], bracketed to adjacent
     // doubles (the root search takes g = -d ln(f^2 A_22)/df, which rises)
     double lo = s.fJ, hi = s.fRD, glo, ghi, fp;
@@ -442,7 +464,8 @@ __device__ void swsh_m2(int l, int m, double th, double ph, double &re, double &
 // weights are left zero.  f_start is the root of t_lm(f) = 0, bracketed to
 // adjacent doubles; f_end = min(band end, (m/2) 0.2 / M).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ ModeBand band_support(const Source &s, int l, int m, const GridDesc &g)
+__device__ __forceinline__ ModeBand band_support(const Source &s, int l, int m, const GridDesc &g,
+                                                 const double *pre = nullptr)
 {
     ModeBand b;
     b.fs = 0.0;
@@ -462,7 +485,18 @@ __device__ __forceinline__ ModeBand band_support(const Source &s, int l, int m, 
         double fs = f_lo;
         if (have) {
             double lo = f_lo, hi = fe, glo, ghi;
-            wave_root(lo, hi, glo, ghi, [&](double x, double &t, double &dt) { mode_time(s, l, m, x, t, dt); });
+            const auto g1 = [&](double x, double &t, double &dt) { mode_time(s, l, m, x, t, dt); };
+            if (pre) {
+                // first round from band_first_round: d phi_22/df and its
+                // derivative at the round's points, aligned here as mode_time does
+                const int lane = threadIdx.x & 63;
+                wave_root(lo, hi, glo, ghi, g1, [&](double, double &t, double &dt) {
+                    t = s.tcoal - (pre[lane] - s.al1) / kTwoPi;
+                    dt = -(2.0 / m) * pre[kRootLanes + lane] / kTwoPi;
+                });
+            } else {
+                wave_root(lo, hi, glo, ghi, g1);
+            }
             if (glo >= 0.0) fs = f_lo;                 // the mode starts before the band
             else if (ghi < 0.0) have = false;          // ... or only after its end
             else fs = hi;
@@ -479,6 +513,26 @@ __device__ __forceinline__ ModeBand band_support(const Source &s, int l, int m, 
         }
     }
     return b;
+}
+
+// The first round of band_support's f_start search for a mode of order m, ahead of
+// the alignment at f_peak (which it does not need): d phi_22/df and its
+// derivative at 2f/m for the round's points f, into pre[lane] and
+// pre[kRootLanes + lane].  Called by a whole wavefront with the walker's
+// constants (source_consts); the same bits as mode_time forms there.
+__device__ __forceinline__ void band_first_round(const Source &s, int m, const GridDesc &g, double *pre)
+{
+    if (!s.valid) return;
+    const double f_lo = (double)g.k0 * g.df;
+    const double f_hi = (double)(g.k0 + g.n - 1) * g.df;
+    const double fe = fmin(0.5 * m * kMfCut / s.M, f_hi);
+    if (!(fe > f_lo)) return;
+    const int lane = threadIdx.x & 63;
+    const double x = wave_root_point(f_lo, fe, lane);
+    double p = 0.0, a = 0.0, b = 0.0;
+    if (lane == 0 || lane == 63 || (x > f_lo && x < fe)) phase22_raw(s, 2.0 * x / m, p, a, b);
+    pre[lane] = a;
+    pre[kRootLanes + lane] = b;
 }
 
 // Plus and cross weights of mode (l, m) (complex, re and im), which depend
@@ -1003,6 +1057,7 @@ __global__ __launch_bounds__(kSplineThreads) void k_sparse(const double *__restr
     __shared__ Source ss;
     __shared__ ModeBand sb;
     __shared__ double swt[4];                      // the mode's K+ and Kx
+    __shared__ double spre[2 * kRootLanes];        // first round of the f_start search
     const int wm = blockIdx.x;
     if (wm >= B * md.nm) return;                   // whole workgroups leave together
     const int w = wm / md.nm, im = wm - w * md.nm;
@@ -1024,10 +1079,13 @@ __global__ __launch_bounds__(kSplineThreads) void k_sparse(const double *__restr
             swt[2] = kc[0];
             swt[3] = kc[1];
         }
+        // then the first round of the mode's f_start search, which needs
+        // every walker constant but the alignment at f_peak
+        band_first_round(source_consts(params + 11 * (size_t)w, g.t0), m, g, spre);
     }
     __syncthreads();
     if (threadIdx.x < kRootLanes) {
-        ModeBand b = band_support(ss, l, m, g);
+        ModeBand b = band_support(ss, l, m, g, spre);
         if (ss.valid) {
             b.kp[0] = swt[0];
             b.kp[1] = swt[1];
